@@ -1,0 +1,156 @@
+/*
+ * apsp.h -- all-pairs shortest-path lengths on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: blocked Floyd-Warshall in three phases per round (Schoeneman & Zola,
+ * arXiv:1902.04446, Sec. 4.4 "Blocked In-Memory" and Sec. 4.5 "Blocked
+ * Collect/Broadcast", Algorithms 3 and 4; the phase operations are Table 1's
+ * FloydWarshall, MinPlus = MatProd followed by MatMin).  The problem is the
+ * one stated in Sec. 3: an undirected weighted graph with no negative cycles,
+ * vertices numbered 0..n-1, adjacency matrix A with A_ij = A_ji = w_ij, and
+ * the output is the length of a shortest path between every pair (no paths).
+ * Dropping the symmetry assumption gives the directed case (Sec. 4), which
+ * this library also accepts: it never relies on A being symmetric.
+ *
+ * Matrix format (every entry point):
+ *   - dense, row-major, n x n, leading dimension ld >= n (in elements),
+ *     resident in device memory of the current HIP device;
+ *   - element type APSP_I32 (int32) or APSP_F32 (fp32);
+ *   - entry (i, j) is the weight of edge i->j; a missing edge is
+ *       APSP_I32: any value >= APSP_INF_I32 (2^30),
+ *       APSP_F32: +inf;
+ *   - weights must be >= 0 (in an undirected graph a negative edge is a
+ *     negative cycle); NaN is not allowed.  apsp_validate() checks this.
+ *     Results for inputs outside this domain are unspecified (no fault).
+ *   - the input diagonal is ignored: the empty path gives D_ii = 0.
+ * Result, in place: D_ij = shortest-path length from i to j; unreachable
+ * pairs hold APSP_INF_I32 (int32) or +inf (fp32).  int32 lengths that would
+ * reach 2^30 or more are reported as APSP_INF_I32.  int32 results are exact;
+ * fp32 results use IEEE round-to-nearest additions, one per path edge.
+ *
+ * Stream semantics: every call enqueues its work on `stream` (a hipStream_t;
+ * NULL = the default stream) and returns before the work completes, except
+ * apsp_validate(), which waits for its own result.  Host arrays passed in may
+ * be reused as soon as a call returns.  The caller owns all device memory it
+ * passes in; the library keeps no pointer to it after the enqueued work ends.
+ *
+ * Errors: arguments are checked on the host before any HIP call; a failed
+ * check returns a status and enqueues nothing.  No C++ exception crosses this
+ * interface.  Faults of the device work itself surface at the caller's next
+ * synchronisation with `stream`.
+ */
+#ifndef APSP_H_
+#define APSP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element types (pass as the int32_t `dtype` argument). */
+enum { APSP_I32 = 0, APSP_F32 = 1 };
+
+/* Status codes. */
+enum {
+    APSP_OK = 0,
+    APSP_ERR_INVALID_VALUE = 1, /* bad size, leading dimension, pointer, dtype or count */
+    APSP_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve */
+    APSP_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
+    APSP_ERR_NO_MEMORY = 4,     /* device workspace could not be allocated */
+    APSP_ERR_BAD_INPUT = 5      /* apsp_validate(): negative weight or NaN found */
+};
+
+/* Sentinel for "no edge" / "unreachable" in int32 matrices. */
+#define APSP_INF_I32 (1 << 30)
+
+/*
+ * apsp_solve -- solve one graph in place (Sec. 4.4/4.5, all q = ceil(n/b)
+ * rounds of the blocked method; b = apsp_round_width()).
+ *   dist   device pointer to the n x n matrix (ld elements per row); may be
+ *          NULL only when n == 0.
+ *   n      number of vertices, 0 <= n <= 2^31 - 1 (n == 0: no-op).
+ *   ld     leading dimension in elements, ld >= max(n, 1).
+ *   dtype  APSP_I32 or APSP_F32.
+ *   stream hipStream_t to enqueue on (NULL = default stream).
+ * Needs no device memory beyond `dist`.
+ * Returns APSP_OK, APSP_ERR_INVALID_VALUE or APSP_ERR_DEVICE.
+ */
+int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
+
+/*
+ * apsp_solve_rounds -- run rounds r0 .. r1-1 of the blocked method only
+ * (Sec. 4.4: each round is phase 1 on diagonal block r, phase 2 on its block
+ * row and block column, phase 3 on every other block).  r0 == 0 also applies
+ * the input normalisation (zero diagonal, int32 entries above 2^30 mapped to
+ * 2^30).  After rounds 0..r-1 the matrix equals Floyd-Warshall stopped after
+ * pivots 0 .. min(r*b, n)-1, so a solve may be split into slices, checkpointed
+ * and resumed between calls.  r1 is clamped to q; r0 >= r1 is a no-op.
+ * Returns as apsp_solve; r0 < 0 or r1 < 0 is APSP_ERR_INVALID_VALUE.
+ */
+int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0,
+                          int64_t r1, void *stream);
+
+/*
+ * apsp_solve_profiled -- apsp_solve with HIP events recorded on `stream`
+ * between the kernel launches; waits for the solve to finish, then writes
+ * the elapsed milliseconds into phase_ms[0..4]:
+ *   [0] input normalisation, [1] all phase-1 launches, [2] all phase-2
+ *   launches, [3] all phase-3 launches, [4] the whole solve.
+ * Each phase figure is measured from the event after the previous launch to
+ * the event after its own launch, so it includes launch gaps.  The result in
+ * `dist` is identical to apsp_solve's.  phase_ms must not be NULL.
+ * Synchronous.  Returns as apsp_solve.
+ */
+int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream,
+                            double *phase_ms);
+
+/* Round width b used by apsp_solve / apsp_solve_rounds (currently 128 for
+ * every n and dtype); q = ceil(n / b) rounds.  Returns 0 for a bad dtype. */
+int32_t apsp_round_width(int64_t n, int32_t dtype);
+
+/*
+ * apsp_solve_batched -- solve `count` independent int32 graphs in one launch.
+ *   ptrs[g]  device pointer to graph g's n_g x n_g int32 matrix (ld = n_g),
+ *            solved in place; graphs must not overlap in memory.
+ *   ns[g]    n_g, 0 <= n_g <= APSP_BATCHED_MAX_N.
+ *   count    number of graphs, >= 0 (0: no-op; ptrs/ns may then be NULL).
+ * Each graph gets exactly the result apsp_solve would give it (int32 is
+ * exact).  Allocates a small stream-ordered device descriptor table.
+ * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY or
+ * APSP_ERR_DEVICE.
+ */
+#define APSP_BATCHED_MAX_N 4096
+int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, void *stream);
+
+/*
+ * apsp_solve_batched_ex -- as apsp_solve_batched with per-graph leading
+ * dimensions (lds[g] >= max(n_g, 1); lds == NULL means ld = n) and a dtype
+ * for the whole batch.  fp32 graphs are solved with the batched round width
+ * (apsp_batched_round_width), so their last bits may differ from apsp_solve;
+ * both are the blocked method in IEEE fp32.
+ */
+int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                              int32_t count, int32_t dtype, void *stream);
+
+/* Round width used inside the batched kernel for a graph of n vertices. */
+int32_t apsp_batched_round_width(int64_t n, int32_t dtype);
+
+/*
+ * apsp_validate -- check the input domain (Sec. 3: non-negative weights, no
+ * NaN) of an n x n matrix.  Synchronous: waits on `stream` for its own result.
+ * Returns APSP_OK when every entry is >= 0 (and not NaN), APSP_ERR_BAD_INPUT
+ * otherwise, or an argument / device error.  The diagonal is checked too.
+ */
+int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
+
+/* Static description of a status code (never NULL). */
+const char *apsp_status_string(int32_t status);
+
+/* Library version string, e.g. "apsp-mi355x 0.1.0 gfx950". */
+const char *apsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APSP_H_ */

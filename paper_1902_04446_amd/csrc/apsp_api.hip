@@ -1,0 +1,208 @@
+// C ABI of the APSP library (declared in include/apsp.h).  Arguments are
+// checked on the host before any HIP call; kernels are enqueued on the
+// caller's stream; nothing here blocks except apsp_validate.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "../../include/apsp.h"
+#include "apsp_common.h"
+
+using apsp::BatchDesc;
+
+namespace {
+
+constexpr int64_t kMaxN = (int64_t)1 << 31;  // exclusive
+
+bool bad_dtype(int32_t dtype) { return dtype != APSP_I32 && dtype != APSP_F32; }
+
+int32_t check_matrix(const void *dist, int64_t n, int64_t ld, int32_t dtype) {
+    if (bad_dtype(dtype)) return APSP_ERR_INVALID_VALUE;
+    if (n < 0 || n >= kMaxN) return APSP_ERR_INVALID_VALUE;
+    if (ld < (n > 1 ? n : 1)) return APSP_ERR_INVALID_VALUE;
+    if (n > 0 && dist == nullptr) return APSP_ERR_INVALID_VALUE;
+    // n x ld elements of 4 bytes must be addressable: n * ld < 2^61
+    if (n > 0 && ld > (((int64_t)1 << 61) / n)) return APSP_ERR_INVALID_VALUE;
+    return APSP_OK;
+}
+
+int32_t rounds_impl(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0, int64_t r1,
+                    void *stream) {
+    const int64_t b = apsp::kRoundB;
+    const int64_t q = (n + b - 1) / b;
+    if (r1 > q) r1 = q;
+    if (n == 0 || r0 >= r1) return APSP_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t *D = static_cast<uint32_t *>(dist);
+    if (r0 == 0 && apsp::launch_prologue(D, n, ld, dtype, s) != hipSuccess)
+        return APSP_ERR_DEVICE;
+    for (int64_t r = r0; r < r1; ++r)
+        if (apsp::launch_round(D, n, ld, dtype, r, s) != hipSuccess) return APSP_ERR_DEVICE;
+    return APSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    return rounds_impl(dist, n, ld, dtype, 0, INT64_MAX, stream);
+}
+
+int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0,
+                          int64_t r1, void *stream) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    if (r0 < 0 || r1 < 0) return APSP_ERR_INVALID_VALUE;
+    return rounds_impl(dist, n, ld, dtype, r0, r1, stream);
+}
+
+int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream,
+                            double *phase_ms) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    if (phase_ms == nullptr) return APSP_ERR_INVALID_VALUE;
+    for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0;
+    if (n == 0) return APSP_OK;
+    const int64_t q = (n + apsp::kRoundB - 1) / apsp::kRoundB;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<hipEvent_t> ev((size_t)(2 + 3 * q), nullptr);
+    int32_t result = APSP_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            result = APSP_ERR_DEVICE;
+        }
+    uint32_t *D = static_cast<uint32_t *>(dist);
+    if (result == APSP_OK) {
+        if (hipEventRecord(ev[0], s) != hipSuccess ||
+            apsp::launch_prologue(D, n, ld, dtype, s) != hipSuccess ||
+            hipEventRecord(ev[1], s) != hipSuccess)
+            result = APSP_ERR_DEVICE;
+        for (int64_t r = 0; r < q && result == APSP_OK; ++r)
+            if (apsp::launch_round(D, n, ld, dtype, r, s, &ev[(size_t)(2 + 3 * r)]) != hipSuccess)
+                result = APSP_ERR_DEVICE;
+    }
+    if (result == APSP_OK && hipEventSynchronize(ev.back()) != hipSuccess) result = APSP_ERR_DEVICE;
+    if (result == APSP_OK) {
+        float ms = 0.f;
+        auto gap = [&](size_t a, size_t b) {
+            return hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess ? (double)ms : 0.0;
+        };
+        phase_ms[0] = gap(0, 1);
+        for (int64_t r = 0; r < q; ++r) {
+            const size_t b = (size_t)(2 + 3 * r);
+            phase_ms[1] += gap(b - 1, b);
+            phase_ms[2] += gap(b, b + 1);
+            phase_ms[3] += gap(b + 1, b + 2);
+        }
+        phase_ms[4] = gap(0, ev.size() - 1);
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return result;
+}
+
+int32_t apsp_round_width(int64_t, int32_t dtype) {
+    return bad_dtype(dtype) ? 0 : apsp::kRoundB;
+}
+
+int32_t apsp_batched_round_width(int64_t n, int32_t dtype) {
+    return bad_dtype(dtype) ? 0 : apsp::batched_tile(n);
+}
+
+int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                              int32_t count, int32_t dtype, void *stream) {
+    if (bad_dtype(dtype) || count < 0) return APSP_ERR_INVALID_VALUE;
+    if (count == 0) return APSP_OK;
+    if (ptrs == nullptr || ns == nullptr) return APSP_ERR_INVALID_VALUE;
+    int max_n = 0;
+    for (int32_t g = 0; g < count; ++g) {
+        const int64_t n = ns[g];
+        const int64_t ld = lds ? lds[g] : (n > 1 ? n : 1);
+        if (n < 0 || n > APSP_BATCHED_MAX_N) return APSP_ERR_INVALID_VALUE;
+        if (ld < (n > 1 ? n : 1)) return APSP_ERR_INVALID_VALUE;
+        if (n > 0 && ptrs[g] == nullptr) return APSP_ERR_INVALID_VALUE;
+        max_n = std::max<int>(max_n, (int)n);
+    }
+    // Longest job first: the hardware dispatches workgroups in order.
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
+    std::vector<BatchDesc> host;
+    host.reserve(count);
+    for (int32_t g : order) {
+        if (ns[g] == 0) continue;
+        BatchDesc d;
+        d.ptr = static_cast<uint32_t *>(ptrs[g]);
+        d.ld = lds ? lds[g] : (ns[g] > 1 ? ns[g] : 1);
+        d.n = ns[g];
+        d.pad_ = 0;
+        host.push_back(d);
+    }
+    if (host.empty()) return APSP_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    void *dev = nullptr;
+    const size_t bytes = host.size() * sizeof(BatchDesc);
+    if (hipMallocAsync(&dev, bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return APSP_ERR_NO_MEMORY;
+    }
+    // Pageable source: the copy has consumed `host` when the call returns.
+    if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+        (void)hipFreeAsync(dev, s);
+        return APSP_ERR_DEVICE;
+    }
+    const hipError_t e = apsp::launch_batched(static_cast<const BatchDesc *>(dev),
+                                              (int32_t)host.size(), max_n, dtype, s);
+    if (hipFreeAsync(dev, s) != hipSuccess || e != hipSuccess) return APSP_ERR_DEVICE;
+    return APSP_OK;
+}
+
+int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, void *stream) {
+    return apsp_solve_batched_ex(ptrs, ns, nullptr, count, APSP_I32, stream);
+}
+
+int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    if (n == 0) return APSP_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t *flag = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&flag), sizeof(uint32_t), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return APSP_ERR_NO_MEMORY;
+    }
+    uint32_t host_flag = 0;
+    int32_t result = APSP_OK;
+    if (hipMemsetAsync(flag, 0, sizeof(uint32_t), s) != hipSuccess ||
+        apsp::launch_validate(static_cast<const uint32_t *>(dist), n, ld, dtype, flag, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        result = APSP_ERR_DEVICE;
+    else if (host_flag != 0)
+        result = APSP_ERR_BAD_INPUT;
+    (void)hipFreeAsync(flag, s);
+    return result;
+}
+
+const char *apsp_status_string(int32_t status) {
+    switch (status) {
+    case APSP_OK: return "APSP_OK";
+    case APSP_ERR_INVALID_VALUE: return "APSP_ERR_INVALID_VALUE: bad size, leading dimension, pointer, dtype or count";
+    case APSP_ERR_UNSUPPORTED: return "APSP_ERR_UNSUPPORTED: request not supported by this build";
+    case APSP_ERR_DEVICE: return "APSP_ERR_DEVICE: a HIP call or kernel launch failed";
+    case APSP_ERR_NO_MEMORY: return "APSP_ERR_NO_MEMORY: device workspace allocation failed";
+    case APSP_ERR_BAD_INPUT: return "APSP_ERR_BAD_INPUT: negative weight or NaN in the matrix";
+    default: return "APSP: unknown status";
+    }
+}
+
+const char *apsp_version(void) { return "apsp-mi355x 0.1.0 gfx950"; }
+
+}  // extern "C"

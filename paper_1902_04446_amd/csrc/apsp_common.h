@@ -1,0 +1,74 @@
+// Shared device helpers and internal launcher declarations of the APSP library.
+//
+// Element arithmetic of the min-plus (tropical) semiring used by every phase
+// of the blocked method (arXiv:1902.04446, Table 1: MatProd is the (min, +)
+// product, MatMin the element-wise minimum).  Both element types are carried
+// as 32-bit words so one kernel body serves both:
+//
+//  * OpI32: int32 weights in [0, 2^30] computed as uint32.  Every stored value
+//    stays <= 2^30 (a minimum always includes the current value), so a sum of
+//    two is <= 2^31 and never wraps; v_add_u32 + v_min3_u32.
+//  * OpF32: fp32 bit patterns.  Weights are >= 0 (or -0), and for such values
+//    the signed-integer order of the bit patterns is the numeric order, with
+//    +inf (0x7f800000) above every finite value.  Taking the minimum on the
+//    bits (v_min3_i32) therefore equals the fp32 minimum and needs no NaN
+//    canonicalisation; the sum is an IEEE fp32 add (v_add_f32).
+//
+// Neither form uses packed fp32 instructions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apsp {
+
+constexpr uint32_t kInfI32 = 1u << 30;
+constexpr uint32_t kInfF32Bits = 0x7f800000u;
+
+struct OpI32 {
+    static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+    static __device__ __forceinline__ uint32_t min2(uint32_t a, uint32_t b) { return a < b ? a : b; }
+    static __device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
+        return min2(min2(a, b), c);
+    }
+    static __device__ __forceinline__ uint32_t pad() { return kInfI32; }
+};
+
+struct OpF32 {
+    static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) {
+        return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+    }
+    static __device__ __forceinline__ uint32_t min2(uint32_t a, uint32_t b) {
+        return (int32_t)a < (int32_t)b ? a : b;
+    }
+    static __device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
+        return min2(min2(a, b), c);
+    }
+    static __device__ __forceinline__ uint32_t pad() { return kInfF32Bits; }
+};
+
+// Round width of the single-graph solver and the output tile of the
+// phase-2/phase-3 kernels (one workgroup per 128 x 128 tile).
+constexpr int kRoundB = 128;
+
+// Per-graph descriptor of a batched solve.
+struct BatchDesc {
+    uint32_t *ptr;
+    int64_t ld;
+    int32_t n;
+    int32_t pad_;
+};
+
+// ---- launchers (host side; each returns a hipError_t) ----------------------
+hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s);
+// One round (phases 1, 2, 3).  If after_phase is non-null, after_phase[i] is
+// recorded on s right after phase i+1 is enqueued.
+hipError_t launch_round(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s,
+                        hipEvent_t *after_phase = nullptr);
+hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,
+                           hipStream_t s);
+hipError_t launch_batched(const BatchDesc *descs_dev, int32_t count, int max_n, int dtype,
+                          hipStream_t s);
+int batched_tile(int64_t n);
+
+}  // namespace apsp

@@ -1,0 +1,150 @@
+"""C-ABI checks that need no GPU: exported symbols, argument validation
+(performed on the host before any HIP call), status strings, and the
+workgroup -> tile index maps of the phase kernels, re-derived here and checked
+for being bijections onto the tiles each phase must cover."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "apsp.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1902_04446_amd as apsp
+
+    return apsp.library()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(apsp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("apsp_solve", "apsp_solve_batched", "apsp_solve_batched_ex",
+                     "apsp_solve_rounds", "apsp_status_string", "apsp_validate"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_1902_04446_amd as apsp
+
+    out = subprocess.run(["nm", "-D", "--defined-only", apsp.lib_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (apsp_\w+)", out))
+    missing = [f for f in _declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in _declared_functions():
+        getattr(lib, f)
+
+
+def test_library_is_built_for_gfx950():
+    import paper_1902_04446_amd as apsp
+
+    out = subprocess.run(["strings", apsp.lib_path()], capture_output=True, text=True).stdout
+    assert "gfx950" in out
+
+
+def test_host_side_argument_validation(lib):
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: every call below fails validation first
+    assert lib.apsp_solve(fake, -1, 4, 0, None) == 1
+    assert lib.apsp_solve(fake, 8, 7, 0, None) == 1          # ld < n
+    assert lib.apsp_solve(None, 8, 8, 0, None) == 1          # NULL with n > 0
+    assert lib.apsp_solve(fake, 8, 8, 7, None) == 1          # bad dtype
+    assert lib.apsp_solve(fake, 1 << 31, 1 << 31, 0, None) == 1
+    assert lib.apsp_solve(None, 0, 1, 0, None) == 0          # n == 0 is a no-op
+    assert lib.apsp_solve(None, 0, 0, 1, None) == 1          # ld >= 1 always
+    assert lib.apsp_solve_rounds(fake, 8, 8, 0, -1, 2, None) == 1
+    assert lib.apsp_solve_rounds(fake, 8, 8, 0, 3, 3, None) == 0   # empty range: no-op
+    assert lib.apsp_solve_rounds(fake, 8, 8, 0, 5, 9, None) == 0   # r0 beyond q: no-op
+    ms = (ctypes.c_double * 5)()
+    assert lib.apsp_solve_profiled(fake, 8, 8, 0, None, None) == 1
+    assert lib.apsp_solve_profiled(None, 0, 1, 0, None, ms) == 0
+    assert lib.apsp_validate(None, 3, 3, 0, None) == 1
+    assert lib.apsp_validate(None, 0, 1, 0, None) == 0
+
+
+def test_batched_argument_validation(lib):
+    vp = ctypes.c_void_p
+    ptrs = (vp * 2)(0x1000, 0x2000)
+    ns = (ctypes.c_int32 * 2)(4, 5)
+    assert lib.apsp_solve_batched(None, None, 0, None) == 0
+    assert lib.apsp_solve_batched(ptrs, ns, -1, None) == 1
+    assert lib.apsp_solve_batched(None, ns, 2, None) == 1
+    bad_n = (ctypes.c_int32 * 2)(4, 5000)
+    assert lib.apsp_solve_batched(ptrs, bad_n, 2, None) == 1
+    neg_n = (ctypes.c_int32 * 2)(4, -1)
+    assert lib.apsp_solve_batched(ptrs, neg_n, 2, None) == 1
+    null_ptrs = (vp * 2)(0x1000, None)
+    assert lib.apsp_solve_batched(null_ptrs, ns, 2, None) == 1
+    lds = (ctypes.c_int64 * 2)(4, 4)  # second ld < n
+    assert lib.apsp_solve_batched_ex(ptrs, ns, lds, 2, 0, None) == 1
+    assert lib.apsp_solve_batched_ex(ptrs, ns, None, 2, 9, None) == 1
+    zero_n = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.apsp_solve_batched(null_ptrs, zero_n, 2, None) == 0  # all empty: no-op
+
+
+def test_status_strings_and_widths(lib):
+    for code in range(6):
+        s = lib.apsp_status_string(code)
+        assert s and s.startswith(b"APSP")
+    assert lib.apsp_status_string(99) == b"APSP: unknown status"
+    assert lib.apsp_round_width(100, 0) == 128 and lib.apsp_round_width(100, 1) == 128
+    assert lib.apsp_round_width(100, 5) == 0
+    assert lib.apsp_batched_round_width(300, 0) == 64
+    assert b"gfx950" in lib.apsp_version()
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+
+    import paper_1902_04446_amd as apsp
+
+    with pytest.raises(ValueError):
+        apsp.solve(torch.zeros(4, 4, dtype=torch.int32))
+    with pytest.raises((TypeError, ValueError)):
+        apsp.solve(torch.zeros(4, 4, dtype=torch.float64))
+
+
+# --------------------------------------------------------------------------
+# Workgroup -> tile maps of the phase-2 and phase-3 launches, re-derived.
+# --------------------------------------------------------------------------
+
+def _phase2_tile(wg, r, q):
+    if wg < q - 1:
+        return r, (wg if wg < r else wg + 1)
+    t = wg - (q - 1)
+    return (t if t < r else t + 1), r
+
+
+def _phase3_tile(wg, r, q):
+    m = q - 1
+    T = m * m
+    x, s = wg & 7, wg >> 3
+    per, rem = T >> 3, T & 7
+    tile = x * per + min(x, rem) + s
+    ti, tj = divmod(tile, m)
+    return (ti if ti < r else ti + 1), (tj if tj < r else tj + 1)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 9, 17, 33])
+def test_phase_tile_maps_are_bijections(q):
+    for r in range(q):
+        p2 = [_phase2_tile(w, r, q) for w in range(2 * (q - 1))]
+        expect2 = {(r, j) for j in range(q) if j != r} | {(i, r) for i in range(q) if i != r}
+        assert len(set(p2)) == len(p2) and set(p2) == expect2
+        p3 = [_phase3_tile(w, r, q) for w in range((q - 1) ** 2)]
+        expect3 = {(i, j) for i in range(q) for j in range(q) if i != r and j != r}
+        assert len(set(p3)) == len(p3) and set(p3) == expect3
+        # each XCD (wg % 8) receives one contiguous run of tiles
+        for x in range(8):
+            ids = [(_phase3_tile(w, r, q)) for w in range(x, (q - 1) ** 2, 8)]
+            assert len(ids) == len(set(ids))

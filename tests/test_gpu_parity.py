@@ -1,0 +1,336 @@
+"""Parity of the HIP path (through the C ABI) with the host oracle, on an MI355X.
+
+int32 results must equal the oracle bit for bit.  fp32 results must equal the
+oracle's blocked fp32 model at the same round width bit for bit (every
+candidate is one IEEE add and the minimum is exact, so tile shapes and k order
+cannot change bits), and lie within 1e-5 relative of the fp64 oracle.  At the
+full workload sizes the oracle checks sampled rows (Dijkstra from sampled
+sources) and the Bellman certificate on them.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+INF = oracle.INF_I32
+REL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def apsp():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_04446_amd as mod
+
+    return mod
+
+
+@pytest.fixture(scope="module")
+def dev(apsp):
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def _to_dev(W, dev, ld=None, offset=0):
+    """Copy a host matrix into a device buffer with leading dimension ld,
+    starting ``offset`` elements into the allocation; returns (view, buffer)."""
+    import torch
+
+    n = W.shape[0]
+    ld = n if ld is None else ld
+    tdt = torch.int32 if W.dtype == np.int32 else torch.float32
+    fill = -7 if tdt == torch.int32 else -3.5  # sentinel for the untouched padding
+    buf = torch.full((offset + max(n, 1) * max(ld, 1),), fill, dtype=tdt, device=dev)
+    view = buf[offset:offset + n * ld].view(n, ld)[:, :n] if n else buf[:0].view(0, 0)
+    if n:
+        view.copy_(torch.from_numpy(np.ascontiguousarray(W)).to(dev))
+    return view, buf
+
+
+def _solve(apsp, W, dev, **kw):
+    import torch
+
+    view, _ = _to_dev(W, dev, **kw)
+    apsp.solve(view)
+    torch.cuda.synchronize()
+    return view.cpu().numpy()
+
+
+def _assert_f32_close(got, ref64):
+    fin = np.isfinite(ref64)
+    assert np.array_equal(fin, np.isfinite(got)), "reachability differs"
+    rel = np.abs(got[fin].astype(np.float64) - ref64[fin]) / np.maximum(ref64[fin], 1e-300)
+    exact_zero = ref64[fin] == 0
+    assert (got[fin][exact_zero] == 0).all()
+    assert rel.max(initial=0.0) <= REL_TOL, f"max rel err {rel.max():.3e}"
+    return float(rel.max(initial=0.0))
+
+
+def _er(n, p, seed, wlo=1, whi=100):
+    u, v, w = gg.er_edges(n, p, wlo, whi, gg.rng_for(gg.CFG_TEST, seed))
+    return gg.dense_from_edges(n, u, v, w, np.int32), (u, v, w)
+
+
+def _swiss(n, seed):
+    u, v, w = gg.swiss_roll_knn(n, gg.CFG_TEST, seed)
+    return gg.dense_from_edges(n, u, v, w, np.float32), (u, v, w)
+
+
+# ------------------------------------------------------------ small config
+
+@pytest.mark.parametrize("item", range(5))
+def test_er512_int32_bit_exact(apsp, dev, item):
+    W, _ = gg.plain_small(item)
+    got = _solve(apsp, W, dev)
+    assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 127, 128, 129, 255, 256, 257, 384, 500])
+def test_shapes_int32(apsp, dev, n):
+    W, _ = _er(n, min(1.0, 3.0 / max(n, 1)), 100 + n)
+    got = _solve(apsp, W, dev)
+    assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8))
+
+
+@pytest.mark.parametrize("n", [1, 2, 129, 256, 300, 513])
+def test_shapes_fp32(apsp, dev, n):
+    W, _ = _swiss(n, 200 + n) if n > 11 else (np.zeros((n, n), np.float32), None)
+    got = _solve(apsp, W, dev)
+    assert np.array_equal(got, oracle.blocked(W, apsp.round_width(n, apsp.APSP_F32)))
+    _assert_f32_close(got, oracle.fw(W, threads=8))
+
+
+@pytest.mark.parametrize("ld_extra,offset", [(1, 0), (4, 0), (212, 0), (0, 1), (3, 3)])
+def test_leading_dimension_and_alignment(apsp, dev, ld_extra, offset):
+    import torch
+
+    n = 300
+    Wi, _ = _er(n, 0.02, 7)
+    Wf, _ = _swiss(n, 8)
+    for W in (Wi, Wf):
+        view, buf = _to_dev(W, dev, ld=n + ld_extra, offset=offset)
+        before = buf.clone()
+        apsp.solve(view)
+        torch.cuda.synchronize()
+        got = view.cpu().numpy()
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8))
+        else:
+            assert np.array_equal(got, oracle.blocked(W, 128))
+        # nothing outside the n x n view was written
+        mask = torch.ones_like(buf, dtype=torch.bool)
+        mask[offset:offset + n * (n + ld_extra)].view(n, n + ld_extra)[:, :n] = False
+        assert torch.equal(buf[mask], before[mask])
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_closed_forms_on_device(apsp, dev):
+    n = 1000
+    i = np.arange(n)
+    path = gg.dense_from_edges(n, i[:-1], i[1:], np.full(n - 1, 3, np.int32), np.int32)
+    assert np.array_equal(_solve(apsp, path, dev).astype(np.int64),
+                          3 * np.abs(i[:, None] - i[None, :]))
+    n = 777
+    i = np.arange(n)
+    cyc = gg.dense_from_edges(n, i, (i + 1) % n, np.full(n, 0.5, np.float32), np.float32)
+    d = np.abs(i[:, None] - i[None, :])
+    assert np.array_equal(_solve(apsp, cyc, dev), (np.minimum(d, n - d) * 0.5).astype(np.float32))
+    r, c = 30, 41
+    idx = np.arange(r * c).reshape(r, c)
+    u = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+    v = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    grid = gg.dense_from_edges(r * c, u, v, np.ones(u.size, np.int32), np.int32)
+    y, x = np.divmod(np.arange(r * c), c)
+    man = np.abs(y[:, None] - y[None, :]) + np.abs(x[:, None] - x[None, :])
+    assert np.array_equal(_solve(apsp, grid, dev).astype(np.int64), man)
+    # disjoint components stay unreachable; empty graph
+    empty = gg.dense_from_edges(200, [], [], np.zeros(0, np.int32), np.int32)
+    exp = np.full((200, 200), INF)
+    np.fill_diagonal(exp, 0)
+    assert np.array_equal(_solve(apsp, empty, dev).astype(np.int64), exp)
+
+
+def test_directed_int32(apsp, dev):
+    rng = gg.rng_for(gg.CFG_TEST, 4242)
+    n = 333
+    W = rng.integers(1, 1000, size=(n, n)).astype(np.int32)
+    W[rng.random((n, n)) > 0.015] = INF
+    assert np.array_equal(_solve(apsp, W, dev).astype(np.int64), oracle.fw(W, threads=8))
+
+
+def test_saturation_and_large_sentinels(apsp, dev):
+    w = (1 << 29) + 7
+    n = 200
+    i = np.arange(n)
+    W = gg.dense_from_edges(n, i[:-1], i[1:], np.full(n - 1, w, np.int32), np.int32)
+    W[5, 100] = np.int32(2**31 - 1)  # above the sentinel: "no edge"
+    assert np.array_equal(_solve(apsp, W, dev).astype(np.int64), oracle.fw(W))
+
+
+# ------------------------------------------------- rounds, resume, profiling
+
+def test_round_state_matches_fw_prefix(apsp, dev):
+    import torch
+
+    n = 400
+    W, _ = _er(n, 0.01, 31)
+    b = apsp.round_width(n, apsp.APSP_I32)
+    for r in (1, 2, 3):
+        view, _ = _to_dev(W, dev)
+        apsp.solve_rounds(view, 0, r)
+        torch.cuda.synchronize()
+        ref = oracle.prepare(W)
+        oracle.fw_steps(ref, 0, min(r * b, n))
+        assert np.array_equal(view.cpu().numpy().astype(np.int64), np.minimum(ref, INF))
+
+
+def test_resume_equals_full_solve(apsp, dev):
+    import torch
+
+    n = 700
+    W, _ = _swiss(n, 32)
+    full = _solve(apsp, W, dev)
+    view, _ = _to_dev(W, dev)
+    q = apsp.num_rounds(n)
+    apsp.solve_rounds(view, 0, 2)
+    torch.cuda.synchronize()
+    snapshot = view.cpu().numpy()
+    # checkpoint -> fresh buffer -> resume
+    view2, _ = _to_dev(snapshot, dev)
+    apsp.solve_rounds(view2, 2, q)
+    torch.cuda.synchronize()
+    assert np.array_equal(view2.cpu().numpy(), full)
+
+
+def test_profiled_equals_plain_and_is_deterministic(apsp, dev):
+    import torch
+
+    n = 700
+    W, _ = _swiss(n, 33)
+    a = _solve(apsp, W, dev)
+    view, _ = _to_dev(W, dev)
+    t = apsp.solve_profiled(view)
+    assert np.array_equal(view.cpu().numpy(), a)
+    assert all(t[k] >= 0 for k in t) and t["total"] > 0 and t["phase3"] > 0
+    b = _solve(apsp, W, dev)
+    assert a.tobytes() == b.tobytes()
+    torch.cuda.synchronize()
+
+
+def test_validate(apsp, dev):
+    import torch
+
+    W, _ = _er(100, 0.05, 34)
+    view, _ = _to_dev(W, dev)
+    assert apsp.validate(view)
+    view[3, 4] = -1
+    assert not apsp.validate(view)
+    Wf, _ = _swiss(100, 35)
+    vf, _ = _to_dev(Wf, dev)
+    assert apsp.validate(vf)
+    vf[1, 2] = float("nan")
+    assert not apsp.validate(vf)
+    vf[1, 2] = -0.0
+    assert apsp.validate(vf)
+    vf[7, 7] = -2.0
+    assert not apsp.validate(vf)
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------- full sizes
+
+def _full_size_swiss(apsp, dev, n, cfg, nsrc, bellman_rows=0):
+    import torch
+
+    u, v, w = gg.swiss_roll_knn(n, cfg, 0)
+    D = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+    apsp.solve(D)  # the configuration the benchmark times
+    torch.cuda.synchronize()
+    csr = gg.csr_from_edges(n, u, v, w)
+    rng = gg.rng_for(gg.CFG_TEST, n)
+    src = np.concatenate([[0, n - 1], rng.choice(np.arange(1, n - 1), size=nsrc, replace=False)])
+    tsrc = torch.as_tensor(src, device=dev)
+    rows = D[tsrc].cpu().numpy()
+    cols = D[:, tsrc].cpu().numpy().T
+    ref = oracle.dijkstra(csr, n, src, threads=16)
+    worst = _assert_f32_close(rows, ref)
+    assert (rows[np.arange(src.size), src] == 0).all()
+    # undirected input: column i holds the same lengths as row i
+    _assert_f32_close(cols, ref)
+    bell = None
+    if bellman_rows:
+        host = D.cpu().numpy()
+        brows = np.concatenate([src, rng.choice(n, size=bellman_rows, replace=False)])
+        bell = oracle.bellman_residual_f32(host, csr, brows, threads=16)
+        assert bell <= REL_TOL, f"Bellman residual {bell:.3e}"
+    return worst, bell
+
+
+def test_full_size_swiss_16384(apsp, dev):
+    worst, bell = _full_size_swiss(apsp, dev, 16384, gg.CFG_SWISS_16K, 48, bellman_rows=2000)
+    print(f"n=16384 fp32: max rel err vs fp64 Dijkstra on sampled rows {worst:.3e}; "
+          f"Bellman residual {bell:.3e}")
+
+
+@pytest.mark.slow
+def test_full_size_swiss_65536(apsp, dev):
+    worst, _ = _full_size_swiss(apsp, dev, 65536, gg.CFG_SWISS_64K, 16)
+    print(f"n=65536 fp32: max rel err vs fp64 Dijkstra on sampled rows {worst:.3e}")
+
+
+# --------------------------------------------------------------- batched
+
+def _batched_case_sizes():
+    return [1, 2, 31, 63, 64, 65, 127, 128, 129, 200, 333, 512]
+
+
+def test_batched_int32_small_cases(apsp, dev):
+    import torch
+
+    Ws = [_er(n, min(1.0, 8.0 / n), 500 + n, 1, 1000)[0] for n in _batched_case_sizes()]
+    views = [_to_dev(W, dev)[0] for W in Ws]
+    apsp.solve_batched(views)
+    torch.cuda.synchronize()
+    for W, v in zip(Ws, views):
+        assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
+
+
+def test_batched_fp32_with_ld(apsp, dev):
+    import torch
+
+    Ws = [_swiss(n, 600 + n)[0] if n > 11 else np.zeros((n, n), np.float32)
+          for n in _batched_case_sizes()]
+    views = [_to_dev(W, dev, ld=W.shape[0] + 3)[0] for W in Ws]
+    apsp.solve_batched(views)
+    torch.cuda.synchronize()
+    for W, v in zip(Ws, views):
+        n = W.shape[0]
+        got = v.cpu().numpy()
+        assert np.array_equal(got, oracle.blocked(W, apsp.batched_round_width(n, apsp.APSP_F32)))
+        _assert_f32_close(got, oracle.fw(W))
+
+
+def test_batched_config_4096_graphs(apsp, dev):
+    """4096 ER graphs, n log-uniform in [32, 512], p = 8/n, int32 U{1..1000}."""
+    import torch
+
+    Ws = gg.batched_graphs(4096, item=0)
+    views = [torch.from_numpy(W).to(dev) for W in Ws]
+    apsp.solve_batched(views)
+    # the same graphs one by one through the single-graph path
+    singles = [torch.from_numpy(W).to(dev) for W in Ws]
+    for s in singles:
+        apsp.solve(s)
+    torch.cuda.synchronize()
+    for v, s in zip(views, singles):
+        assert torch.equal(v, s)
+    sample = gg.rng_for(gg.CFG_TEST, 4096).choice(len(Ws), size=96, replace=False)
+    for g in sample:
+        assert np.array_equal(views[g].cpu().numpy().astype(np.int64), oracle.fw(Ws[g])), g
