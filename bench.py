@@ -32,13 +32,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# = 39.32e12 lane-instructions/s.  A min-plus update needs one add and one
-# min; with k-paired candidates two updates cost 2 adds + 1 three-input min
-# (no packed fp32 instructions are used), i.e. 1.5 instructions per update.
-VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
-INSTR_PER_UPDATE = 1.5
-VALU_PEAK_UPD = VALU_LANE_INSTR_PER_S / INSTR_PER_UPDATE
+# VALU ceiling of MI355X for the min-plus update, from unit counts and clock:
+# 256 CUs at 2.4 GHz.  fp32/int32 adds issue at 128 lanes/clk/CU (the 157.3
+# TFLOP/s fp32 vector figure is 256 x 128 x 2 flops x 2.4e9); min/max-class
+# instructions (v_min3_i32, v_min3_u32) issue at half that, 64 lanes/clk/CU
+# (measured by the VALU probe below).  Two updates with k-paired candidates
+# cost 2 adds + 1 three-input min: 2/128 + 1/64 = 2/64 CU-clock-lanes, so
+# 64 updates per clock per CU.
+CUS, CLOCK_HZ = 256, 2.4e9
+ADD_LANES_PER_CLK, MIN_LANES_PER_CLK = 128, 64
+UPDATES_PER_CLK_PER_CU = 1.0 / (1.0 / ADD_LANES_PER_CLK + 0.5 / MIN_LANES_PER_CLK)
+VALU_PEAK_UPD = CUS * CLOCK_HZ * UPDATES_PER_CLK_PER_CU   # 39.32e12 updates/s
+
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_04446_amd", "csrc", "apsp_plain.hip")
 
 
 def cell_updates_per_s(n: int, seconds: float) -> float:
@@ -51,14 +59,54 @@ def log(msg: str) -> None:
     sys.stderr.flush()
 
 
-def phase3_updates(n: int, b: int) -> int:
-    """Algorithmic cell updates of all phase-3 launches of one solve: round r
-    updates every entry outside block row/column r with |K_r| candidates."""
+def phase3_rest_updates(n: int, b: int) -> tuple[int, int]:
+    """Algorithmic cell updates of the phase-3 "rest" launches of one solve
+    (every round r but the last: the entries outside block rows/columns r and
+    r+1, each with |K_r| candidates) and the number of such launches."""
+    q = -(-n // b)
     total = 0
-    for kb in range(0, n, b):
-        kw = min(b, n - kb)
-        total += (n - kw) ** 2 * kw
-    return total
+    for r in range(q - 1):
+        kw = min(b, n - r * b)
+        kw1 = min(b, n - (r + 1) * b)
+        total += (n - kw - kw1) ** 2 * kw
+    return total, q - 1
+
+
+def valu_probe() -> dict | None:
+    """Measured lane-instruction rates of the update's instructions on this GPU."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_1902_04446_amd", "libapsp_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    rates = (ctypes.c_double * 4)()
+    if lib.apsp_probe_valu_rates(rates) != 0:
+        return None
+    add_f32, add_u32, min3_i32, min3_u32 = (float(x) for x in rates)
+    ceiling = 1.0 / (1.0 / add_f32 + 0.5 / min3_i32)
+    return {"unit": "T lane-instr/s", "v_add_f32": round(add_f32 / 1e12, 2),
+            "v_add_u32": round(add_u32 / 1e12, 2), "v_min3_i32": round(min3_i32 / 1e12, 2),
+            "v_min3_u32": round(min3_u32 / 1e12, 2),
+            "measured_update_ceiling_T": round(ceiling / 1e12, 2)}
+
+
+def phase3_traffic() -> float | None:
+    """HBM bytes per phase-3 launch from the committed rocprofv3 counter runs,
+    or None when the kernel source changed since those counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src:
+        return None
+    return float(kv["bytes_per_launch"])
 
 
 def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
@@ -114,7 +162,13 @@ def main() -> int:
     u, v, w = gg.swiss_roll_knn(n, gg.CFG_SWISS_16K if n == 16384 else gg.CFG_TEST, 0)
     pristine = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
     work = torch.empty_like(pristine)
+    # a plain elementwise read+write of the matrix: the calibration kernel for
+    # the FETCH_SIZE / WRITE_SIZE counter runs (outside the timed region)
+    torch.neg(pristine, out=work)
     torch.cuda.synchronize()
+    probe = valu_probe()
+    if probe:
+        log(f"VALU probe: {probe}")
     b = apsp.round_width(n, apsp.APSP_F32)
 
     def step():
@@ -125,7 +179,8 @@ def main() -> int:
         t = step()
         log(f"warmup {i}: {t['total']:.1f} ms")
     torch.cuda.synchronize()
-    phases = {"prologue": 0.0, "phase1": 0.0, "phase2": 0.0, "phase3": 0.0, "total": 0.0}
+    phases = {"prologue": 0.0, "phase1": 0.0, "phase2": 0.0, "phase3": 0.0, "total": 0.0,
+              "phase3_rest": 0.0, "phase3_rest_launches": 0.0, "phase3_other": 0.0}
     t0 = time.perf_counter()
     for i in range(args.steps):
         t = step()
@@ -138,20 +193,29 @@ def main() -> int:
     value = K * float(n) ** 3 / elapsed
     phase_ms = {k: round(vv / K, 3) for k, vv in phases.items()}
 
-    p3_upd = phase3_updates(n, b)
-    p3_s = phases["phase3"] / K / 1e3
     q = -(-n // b)
-    achieved = p3_upd / p3_s
+    rest_upd, rest_launches = phase3_rest_updates(n, b)
+    launches = phases["phase3_rest_launches"] / K
+    if q >= 3 and launches == rest_launches:
+        kernel = "k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles)"
+        launch_s = phases["phase3_rest"] / K / 1e3 / rest_launches
+        per_launch = rest_upd / rest_launches
+    else:  # no lookahead split at this size: whole phase 3 in one launch per round
+        kernel = "k_tiles<kAll> (phase 3, 128x128 tiles)"
+        launch_s = phases["phase3"] / K / 1e3 / q
+        per_launch = sum((n - min(b, n - r * b)) ** 2 * min(b, n - r * b) for r in range(q)) / q
+    achieved = per_launch / launch_s
+    traffic = phase3_traffic()
     roofline = {
         "bound": "alu",
-        "kernel": "k_tiles<phase 3> (128x128 min-plus tile update)",
+        "kernel": kernel,
         "achieved": round(achieved / 1e12, 3),
         "peak": round(VALU_PEAK_UPD / 1e12, 3),
         "unit": "T cell-updates/s",
         "frac": round(achieved / VALU_PEAK_UPD, 4),
-        "traffic": None,
-        "per_launch_updates": round(p3_upd / max(q - 1, 1)),
-        "avg_launch_ms": round(phases["phase3"] / K / max(q - 1, 1), 4),
+        "traffic": traffic,
+        "per_launch_updates": round(per_launch),
+        "avg_launch_ms": round(launch_s * 1e3, 4),
     }
 
     cpu = None
@@ -177,6 +241,7 @@ def main() -> int:
         "phase_ms": phase_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "valu_probe": probe,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -72,8 +72,14 @@ enum {
  *   ld     leading dimension in elements, ld >= max(n, 1).
  *   dtype  APSP_I32 or APSP_F32.
  *   stream hipStream_t to enqueue on (NULL = default stream).
- * Needs no device memory beyond `dist`.
- * Returns APSP_OK, APSP_ERR_INVALID_VALUE or APSP_ERR_DEVICE.
+ * Needs no device memory beyond `dist`.  For n > 256 the phases of round
+ * r+1 overlap the bulk of round r's phase 3 on a library-owned helper stream
+ * (one per device and caller stream, created on first use and kept); the
+ * call makes `stream` wait for that work, so stream order is preserved.
+ * Solves enqueued on the same stream from several host threads are
+ * serialised by the library.
+ * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY (helper stream
+ * could not be created) or APSP_ERR_DEVICE.
  */
 int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
 
@@ -91,14 +97,17 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
                           int64_t r1, void *stream);
 
 /*
- * apsp_solve_profiled -- apsp_solve with HIP events recorded on `stream`
- * between the kernel launches; waits for the solve to finish, then writes
- * the elapsed milliseconds into phase_ms[0..4]:
- *   [0] input normalisation, [1] all phase-1 launches, [2] all phase-2
- *   launches, [3] all phase-3 launches, [4] the whole solve.
- * Each phase figure is measured from the event after the previous launch to
- * the event after its own launch, so it includes launch gaps.  The result in
- * `dist` is identical to apsp_solve's.  phase_ms must not be NULL.
+ * apsp_solve_profiled -- apsp_solve with HIP events recorded around every
+ * launch; waits for the solve to finish, then writes into phase_ms[0..7]:
+ *   [0] input normalisation (ms)
+ *   [1] phase 1, summed over rounds        [2] phase 2, summed over rounds
+ *   [3] phase 3, summed over its launches  [4] the whole solve
+ *   [5] the phase-3 launches that run on the helper stream (all of phase 3
+ *       except block row/column r+1), summed   [6] how many such launches
+ *   [7] the other phase-3 launches, summed
+ * Phase-3 launches overlap phases 1 and 2 of the next round (one-round
+ * lookahead), so [1] + [2] + [3] can exceed [4].  The result in `dist` is
+ * identical to apsp_solve's.  phase_ms must have room for 8 values.
  * Synchronous.  Returns as apsp_solve.
  */
 int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream,

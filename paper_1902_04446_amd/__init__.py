@@ -135,14 +135,17 @@ def solve(t, stream=None):
 def solve_profiled(t, stream=None) -> dict:
     """Solve in place, timing each phase with HIP events on the stream; synchronous.
 
-    Returns milliseconds: {"prologue", "phase1", "phase2", "phase3", "total"}.
+    Returns milliseconds {"prologue", "phase1", "phase2", "phase3", "total",
+    "phase3_rest", "phase3_rest_launches", "phase3_other"}; see apsp_solve_profiled.
     """
     ptr, n, ld, dt = _matrix_args(t)
-    out = (ctypes.c_double * 5)()
+    out = (ctypes.c_double * 8)()
     with _device_of(t):
         _check(_LIB.apsp_solve_profiled(ctypes.c_void_p(ptr), n, ld, dt, _stream(stream), out),
                "apsp_solve_profiled")
-    return dict(zip(("prologue", "phase1", "phase2", "phase3", "total"), list(out)))
+    keys = ("prologue", "phase1", "phase2", "phase3", "total", "phase3_rest",
+            "phase3_rest_launches", "phase3_other")
+    return dict(zip(keys, list(out)))
 
 
 def solve_rounds(t, r0: int, r1: int, stream=None):

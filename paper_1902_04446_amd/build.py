@@ -9,8 +9,11 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["apsp_plain.hip", "apsp_batched.hip", "apsp_api.hip"]
+SOURCES = ["apsp_plain.hip", "apsp_runtime.hip", "apsp_batched.hip", "apsp_api.hip"]
 LIB = os.path.join(HERE, "libapsp.so")
+# diagnostic: VALU issue-rate probe used by the benchmark to state its ceiling
+PROBE_SOURCES = ["valu_probe.hip"]
+PROBE_LIB = os.path.join(HERE, "libapsp_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -27,8 +30,8 @@ FLAGS = [
 ]
 
 
-def build(extra=(), out=LIB, verbose=False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def _compile(sources, out, extra, verbose):
+    srcs = [os.path.join(CSRC, s) for s in sources]
     tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
     if verbose:
@@ -36,9 +39,14 @@ def build(extra=(), out=LIB, verbose=False) -> str:
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libapsp.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
     os.replace(tmp, out)
     return out
+
+
+def build(extra=(), out=LIB, verbose=False) -> str:
+    _compile(PROBE_SOURCES, PROBE_LIB, extra, verbose)
+    return _compile(SOURCES, out, extra, verbose)
 
 
 if __name__ == "__main__":

@@ -27,18 +27,12 @@ int32_t check_matrix(const void *dist, int64_t n, int64_t ld, int32_t dtype) {
 }
 
 int32_t rounds_impl(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0, int64_t r1,
-                    void *stream) {
-    const int64_t b = apsp::kRoundB;
-    const int64_t q = (n + b - 1) / b;
-    if (r1 > q) r1 = q;
-    if (n == 0 || r0 >= r1) return APSP_OK;
+                    void *stream, apsp::PhaseTimes *times) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint32_t *D = static_cast<uint32_t *>(dist);
-    if (r0 == 0 && apsp::launch_prologue(D, n, ld, dtype, s) != hipSuccess)
-        return APSP_ERR_DEVICE;
-    for (int64_t r = r0; r < r1; ++r)
-        if (apsp::launch_round(D, n, ld, dtype, r, s) != hipSuccess) return APSP_ERR_DEVICE;
-    return APSP_OK;
+    const hipError_t e = apsp::run_rounds(static_cast<uint32_t *>(dist), n, ld, dtype, r0, r1,
+                                          r0 == 0, s, times);
+    if (e == hipErrorOutOfMemory) return APSP_ERR_NO_MEMORY;
+    return e == hipSuccess ? APSP_OK : APSP_ERR_DEVICE;
 }
 
 }  // namespace
@@ -48,7 +42,7 @@ extern "C" {
 int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {
     const int32_t st = check_matrix(dist, n, ld, dtype);
     if (st != APSP_OK) return st;
-    return rounds_impl(dist, n, ld, dtype, 0, INT64_MAX, stream);
+    return rounds_impl(dist, n, ld, dtype, 0, INT64_MAX, stream, nullptr);
 }
 
 int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0,
@@ -56,7 +50,7 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
     const int32_t st = check_matrix(dist, n, ld, dtype);
     if (st != APSP_OK) return st;
     if (r0 < 0 || r1 < 0) return APSP_ERR_INVALID_VALUE;
-    return rounds_impl(dist, n, ld, dtype, r0, r1, stream);
+    return rounds_impl(dist, n, ld, dtype, r0, r1, stream, nullptr);
 }
 
 int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream,
@@ -64,45 +58,10 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
     const int32_t st = check_matrix(dist, n, ld, dtype);
     if (st != APSP_OK) return st;
     if (phase_ms == nullptr) return APSP_ERR_INVALID_VALUE;
-    for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0;
-    if (n == 0) return APSP_OK;
-    const int64_t q = (n + apsp::kRoundB - 1) / apsp::kRoundB;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::vector<hipEvent_t> ev((size_t)(2 + 3 * q), nullptr);
-    int32_t result = APSP_OK;
-    for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            e = nullptr;
-            result = APSP_ERR_DEVICE;
-        }
-    uint32_t *D = static_cast<uint32_t *>(dist);
-    if (result == APSP_OK) {
-        if (hipEventRecord(ev[0], s) != hipSuccess ||
-            apsp::launch_prologue(D, n, ld, dtype, s) != hipSuccess ||
-            hipEventRecord(ev[1], s) != hipSuccess)
-            result = APSP_ERR_DEVICE;
-        for (int64_t r = 0; r < q && result == APSP_OK; ++r)
-            if (apsp::launch_round(D, n, ld, dtype, r, s, &ev[(size_t)(2 + 3 * r)]) != hipSuccess)
-                result = APSP_ERR_DEVICE;
-    }
-    if (result == APSP_OK && hipEventSynchronize(ev.back()) != hipSuccess) result = APSP_ERR_DEVICE;
-    if (result == APSP_OK) {
-        float ms = 0.f;
-        auto gap = [&](size_t a, size_t b) {
-            return hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess ? (double)ms : 0.0;
-        };
-        phase_ms[0] = gap(0, 1);
-        for (int64_t r = 0; r < q; ++r) {
-            const size_t b = (size_t)(2 + 3 * r);
-            phase_ms[1] += gap(b - 1, b);
-            phase_ms[2] += gap(b, b + 1);
-            phase_ms[3] += gap(b + 1, b + 2);
-        }
-        phase_ms[4] = gap(0, ev.size() - 1);
-    }
-    for (auto e : ev)
-        if (e) (void)hipEventDestroy(e);
-    return result;
+    apsp::PhaseTimes t;
+    const int32_t res = rounds_impl(dist, n, ld, dtype, 0, INT64_MAX, stream, &t);
+    for (int i = 0; i < 8; ++i) phase_ms[i] = (res == APSP_OK) ? t.ms[i] : 0.0;
+    return res;
 }
 
 int32_t apsp_round_width(int64_t, int32_t dtype) {

@@ -59,16 +59,36 @@ struct BatchDesc {
     int32_t pad_;
 };
 
+// Tile sets of the min-plus tile kernel (round r, q rounds):
+constexpr int kPanels = 0;  // phase 2: block row r and block column r, 2(q-1) tiles
+constexpr int kAll = 1;     // phase 3: every tile outside block row/column r, (q-1)^2
+constexpr int kNext = 2;    // phase 3, tiles in block row/column r+1, 2q-3
+constexpr int kRest = 3;    // phase 3, tiles outside block rows/columns r, r+1, (q-2)^2
+
 // ---- launchers (host side; each returns a hipError_t) ----------------------
 hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s);
-// One round (phases 1, 2, 3).  If after_phase is non-null, after_phase[i] is
-// recorded on s right after phase i+1 is enqueued.
-hipError_t launch_round(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s,
-                        hipEvent_t *after_phase = nullptr);
+hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s);
+// close_next_diag (kNext only): the workgroup of diagonal block r+1 also runs
+// phase 1 of round r+1 on it before storing it.
+hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
+                           hipStream_t s, bool close_next_diag = false);
+int64_t num_rounds(int64_t n);
+int64_t tile_count(int64_t n, int64_t r, int set);
 hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,
                            hipStream_t s);
 hipError_t launch_batched(const BatchDesc *descs_dev, int32_t count, int max_n, int dtype,
                           hipStream_t s);
 int batched_tile(int64_t n);
+
+// ---- round scheduler (apsp_runtime.hip) ------------------------------------
+// Per-phase elapsed milliseconds of a profiled solve (see apsp_solve_profiled).
+struct PhaseTimes {
+    double ms[8];
+};
+// Enqueue rounds r0..r1-1 (r1 clamped to q) on stream s, with the input
+// normalisation first when `prologue`.  `times` (nullable) requests event
+// timing; the call then waits for completion before filling it in.
+hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0, int64_t r1,
+                      bool prologue, hipStream_t s, PhaseTimes *times);
 
 }  // namespace apsp

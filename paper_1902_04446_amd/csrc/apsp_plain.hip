@@ -29,6 +29,7 @@ constexpr int TB = kRoundB;  // round width == output tile edge
 constexpr int KC = 16;       // k values per LDS stage
 constexpr int NT = 256;      // threads per tile workgroup
 
+
 __device__ __forceinline__ uint4 ld4(const uint32_t *p) {
     return *reinterpret_cast<const uint4 *>(p);
 }
@@ -134,6 +135,66 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 }
 
 // ---------------------------------------------------------------------------
+// Floyd-Warshall closure of a (kw x kw, kw <= 128) diagonal block held in
+// registers in the layout of k_tiles (thread (tx, ty) holds rows
+// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).  Pivot k:
+// the 16 threads holding row k and the 16 holding column k publish them to
+// LDS (double-buffered, one barrier per pivot), then every thread applies
+// d_ij = min(d_ij, d_ik + d_kj) to its 64 entries.  Same operations in the
+// same order as k_phase1, so the same bits.  `lds` needs 4 x 128 words.
+// ---------------------------------------------------------------------------
+template <class Op>
+__device__ __forceinline__ void close_block(uint32_t (&acc)[8][8], int kw, int tx, int ty,
+                                            uint32_t *lds) {
+    uint32_t *rowbuf = lds;            // [2][128]
+    uint32_t *colbuf = lds + 2 * TB;   // [2][128]
+    // pivots in ascending order: k = kh*64 + kq*4 + u
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+        for (int kq = 0; kq < 16; ++kq) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kh * 64 + kq * 4 + u;
+                if (k < kw) {
+                    const int sel = (k & 1) * TB;
+                    const int mk = kh * 4 + u;  // register row/column index of pivot k
+                    if (ty == kq) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&rowbuf[sel + h * 64 + tx * 4]) =
+                                make_uint4(acc[mk][h * 4 + 0], acc[mk][h * 4 + 1],
+                                           acc[mk][h * 4 + 2], acc[mk][h * 4 + 3]);
+                    }
+                    if (tx == kq) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&colbuf[sel + h * 64 + ty * 4]) =
+                                make_uint4(acc[h * 4 + 0][mk], acc[h * 4 + 1][mk],
+                                           acc[h * 4 + 2][mk], acc[h * 4 + 3][mk]);
+                    }
+                    __syncthreads();
+                    uint32_t dik[8], dkj[8];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint4 c4 = *reinterpret_cast<const uint4 *>(&colbuf[sel + h * 64 + ty * 4]);
+                        const uint4 r4 = *reinterpret_cast<const uint4 *>(&rowbuf[sel + h * 64 + tx * 4]);
+                        dik[h * 4 + 0] = c4.x; dik[h * 4 + 1] = c4.y;
+                        dik[h * 4 + 2] = c4.z; dik[h * 4 + 3] = c4.w;
+                        dkj[h * 4 + 0] = r4.x; dkj[h * 4 + 1] = r4.y;
+                        dkj[h * 4 + 2] = r4.z; dkj[h * 4 + 3] = r4.w;
+                    }
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            acc[m][e] = Op::min2(acc[m][e], Op::add(dik[m], dkj[e]));
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Phases 2 and 3: C = min(C, A (x) B) on a 128 x 128 output tile C at
 // (i0, j0), A = D[i0.., K] (128 x kw), B = D[K, j0..] (kw x 128).
 //
@@ -148,12 +209,12 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 // ---------------------------------------------------------------------------
 template <class Op, int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(
-    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec) {
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag) {
     __shared__ uint2 As[2][KC / 2][TB];
     __shared__ uint4 Bs[2][KC][TB / 4];
 
     int I, J;
-    if (MODE == 2) {
+    if (MODE == kPanels) {
         int tt = blockIdx.x;
         if (tt < q - 1) {
             I = r;
@@ -163,19 +224,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             J = r;
             I = tt < r ? tt : tt + 1;
         }
+    } else if (MODE == kNext) {
+        // block row r+1 (every column but r), then block column r+1 (every
+        // row but r and r+1): the tiles the next round's phases 1 and 2 read
+        int tt = blockIdx.x;
+        if (tt < q - 1) {
+            I = r + 1;
+            J = tt < r ? tt : tt + 1;
+        } else {
+            tt -= q - 1;
+            J = r + 1;
+            I = tt < r ? tt : tt + 2;
+        }
     } else {
+        // kAll: every block row/column but r; kRest: every one but r, r+1.
         // Workgroups are dealt round-robin to the 8 XCDs (wg % 8); give each
         // XCD a contiguous range of tiles so tiles sharing panel blocks share
         // that XCD's L2.
-        const int m = q - 1;
+        const int skip = (MODE == kRest) ? 2 : 1;
+        const int m = q - skip;
         const int T = m * m;
         const int wg = blockIdx.x;
         const int x = wg & 7, s = wg >> 3;
         const int per = T >> 3, rem = T & 7;
         const int tile = x * per + (x < rem ? x : rem) + s;
         const int ti = tile / m, tj = tile - ti * m;
-        I = ti < r ? ti : ti + 1;
-        J = tj < r ? tj : tj + 1;
+        I = ti < r ? ti : ti + skip;
+        J = tj < r ? tj : tj + skip;
     }
 
     const int64_t i0 = (int64_t)I * TB, j0 = (int64_t)J * TB, kb = (int64_t)r * TB;
@@ -285,6 +360,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         __syncthreads();
     }
 
+    // Phase 1 of round r+1, fused: the workgroup that just produced diagonal
+    // block r+1 closes it in registers before storing it (classic
+    // Floyd-Warshall over its pivots; see close_block).
+    if (MODE == kNext && close_diag && I == r + 1 && J == r + 1)
+        close_block<Op>(acc, mr, tx, ty, reinterpret_cast<uint32_t *>(&As[0][0][0]));
+
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int row = (m >> 2) * 64 + ty * 4 + (m & 3);
@@ -311,6 +392,25 @@ inline bool aligned16(const void *p, int64_t ld) {
 
 inline unsigned grid_rows(int64_t n) { return (unsigned)(n < 8192 ? n : 8192); }
 
+template <class Op>
+void launch_tiles(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec, int close,
+                  hipStream_t s, unsigned grid) {
+    switch (set) {
+    case kPanels:
+        hipLaunchKernelGGL((k_tiles<Op, kPanels>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        break;
+    case kAll:
+        hipLaunchKernelGGL((k_tiles<Op, kAll>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        break;
+    case kNext:
+        hipLaunchKernelGGL((k_tiles<Op, kNext>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        break;
+    default:
+        hipLaunchKernelGGL((k_tiles<Op, kRest>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        break;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s) {
@@ -333,36 +433,42 @@ hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, 
     return hipGetLastError();
 }
 
-hipError_t launch_round(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s,
-                        hipEvent_t *after_phase) {
+int64_t num_rounds(int64_t n) { return (n + TB - 1) / TB; }
+
+int64_t tile_count(int64_t n, int64_t r, int set) {
+    const int64_t q = num_rounds(n);
+    if (r < 0 || r >= q) return 0;
+    switch (set) {
+    case kPanels: return 2 * (q - 1);
+    case kAll: return (q - 1) * (q - 1);
+    case kNext: return (r + 1 < q) ? 2 * q - 3 : 0;
+    case kRest: return (r + 1 < q) ? (q - 2) * (q - 2) : 0;
+    default: return 0;
+    }
+}
+
+hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s) {
     const int64_t kb = r * TB;
     if (kb >= n) return hipSuccess;
     const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
-    const int q = (int)((n + TB - 1) / TB);
-    const int vec = aligned16(D, ld) ? 1 : 0;
-    const dim3 g2(2 * (q - 1)), g3((unsigned)(q - 1) * (unsigned)(q - 1));
-    auto mark = [&](int ph) {
-        if (after_phase) (void)hipEventRecord(after_phase[ph], s);
-    };
-    if (dtype == 0) {
+    if (dtype == 0)
         hipLaunchKernelGGL(k_phase1<OpI32>, dim3(1), dim3(1024), 0, s, D, ld, kb, kw);
-        mark(0);
-        if (q > 1)
-            hipLaunchKernelGGL((k_tiles<OpI32, 2>), g2, dim3(NT), 0, s, D, ld, n, (int)r, q, vec);
-        mark(1);
-        if (q > 1)
-            hipLaunchKernelGGL((k_tiles<OpI32, 3>), g3, dim3(NT), 0, s, D, ld, n, (int)r, q, vec);
-        mark(2);
-    } else {
+    else
         hipLaunchKernelGGL(k_phase1<OpF32>, dim3(1), dim3(1024), 0, s, D, ld, kb, kw);
-        mark(0);
-        if (q > 1)
-            hipLaunchKernelGGL((k_tiles<OpF32, 2>), g2, dim3(NT), 0, s, D, ld, n, (int)r, q, vec);
-        mark(1);
-        if (q > 1)
-            hipLaunchKernelGGL((k_tiles<OpF32, 3>), g3, dim3(NT), 0, s, D, ld, n, (int)r, q, vec);
-        mark(2);
-    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
+                           hipStream_t s, bool close_next_diag) {
+    const int64_t count = tile_count(n, r, set);
+    if (count <= 0) return hipSuccess;
+    const int q = (int)num_rounds(n);
+    const int vec = aligned16(D, ld) ? 1 : 0;
+    const int close = (set == kNext && close_next_diag) ? 1 : 0;
+    if (dtype == 0)
+        launch_tiles<OpI32>(set, D, n, ld, (int)r, q, vec, close, s, (unsigned)count);
+    else
+        launch_tiles<OpF32>(set, D, n, ld, (int)r, q, vec, close, s, (unsigned)count);
     return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def test_host_side_argument_validation(lib):
     assert lib.apsp_solve_rounds(fake, 8, 8, 0, -1, 2, None) == 1
     assert lib.apsp_solve_rounds(fake, 8, 8, 0, 3, 3, None) == 0   # empty range: no-op
     assert lib.apsp_solve_rounds(fake, 8, 8, 0, 5, 9, None) == 0   # r0 beyond q: no-op
-    ms = (ctypes.c_double * 5)()
+    ms = (ctypes.c_double * 8)()
     assert lib.apsp_solve_profiled(fake, 8, 8, 0, None, None) == 1
     assert lib.apsp_solve_profiled(None, 0, 1, 0, None, ms) == 0
     assert lib.apsp_validate(None, 3, 3, 0, None) == 1
@@ -125,14 +125,24 @@ def _phase2_tile(wg, r, q):
     return (t if t < r else t + 1), r
 
 
-def _phase3_tile(wg, r, q):
-    m = q - 1
+def _phase3_tile(wg, r, q, skip=1):
+    # skip = 1: every tile outside block row/column r;
+    # skip = 2: every tile outside block rows/columns r and r+1
+    m = q - skip
     T = m * m
     x, s = wg & 7, wg >> 3
     per, rem = T >> 3, T & 7
     tile = x * per + min(x, rem) + s
     ti, tj = divmod(tile, m)
-    return (ti if ti < r else ti + 1), (tj if tj < r else tj + 1)
+    return (ti if ti < r else ti + skip), (tj if tj < r else tj + skip)
+
+
+def _next_tile(wg, r, q):
+    # block row r+1 (all columns but r), then block column r+1 (rows but r, r+1)
+    if wg < q - 1:
+        return r + 1, (wg if wg < r else wg + 1)
+    t = wg - (q - 1)
+    return (t if t < r else t + 2), r + 1
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 9, 17, 33])
@@ -148,3 +158,10 @@ def test_phase_tile_maps_are_bijections(q):
         for x in range(8):
             ids = [(_phase3_tile(w, r, q)) for w in range(x, (q - 1) ** 2, 8)]
             assert len(ids) == len(set(ids))
+        if r + 1 < q:
+            # lookahead split of phase 3: next set + rest set = the whole phase
+            nxt = [_next_tile(w, r, q) for w in range(2 * q - 3)]
+            rest = [_phase3_tile(w, r, q, skip=2) for w in range((q - 2) ** 2)]
+            assert len(set(nxt)) == len(nxt) and len(set(rest)) == len(rest)
+            assert set(nxt) | set(rest) == expect3 and not set(nxt) & set(rest)
+            assert set(nxt) == {t for t in expect3 if r + 1 in t}

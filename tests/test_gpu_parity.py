@@ -219,6 +219,7 @@ def test_profiled_equals_plain_and_is_deterministic(apsp, dev):
     t = apsp.solve_profiled(view)
     assert np.array_equal(view.cpu().numpy(), a)
     assert all(t[k] >= 0 for k in t) and t["total"] > 0 and t["phase3"] > 0
+    assert t["phase3_rest_launches"] == apsp.num_rounds(n) - 1
     b = _solve(apsp, W, dev)
     assert a.tobytes() == b.tobytes()
     torch.cuda.synchronize()
