@@ -135,12 +135,74 @@ def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
                       f"{n / k * dt:.0f} s"}
 
 
+def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
+    """Many small graphs: one batched launch vs a loop of single-graph solves.
+
+    4096 ER graphs, n log-uniform in [32, 512], p = 8/n, int32 U{1..1000}.
+    The metric is sum(n_i^3) / t over the whole batch.
+    """
+    import graphgen as gg
+
+    log(f"batched: generating {count} graphs")
+    Ws = gg.batched_graphs(count, item=0)
+    sum_n3 = float(sum(int(W.shape[0]) ** 3 for W in Ws))
+    pristine = [torch.from_numpy(W).to(dev) for W in Ws]
+    # each graph in its own buffer with the row length rounded up to 4
+    # elements (16-byte rows), the layout the vector loads need
+    work = []
+    for p_ in pristine:
+        n_ = p_.shape[0]
+        work.append(torch.empty((n_, (n_ + 3) // 4 * 4), dtype=p_.dtype, device=dev)[:, :n_])
+
+    def reset():
+        for w_, p_ in zip(work, pristine):
+            w_.copy_(p_)
+
+    def timed(fn):
+        best = float("inf")
+        for _ in range(reps):
+            reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    plan = apsp.BatchPlan(work)
+    t_batched = timed(plan.run)
+    ref = [w_.clone() for w_ in work]
+    t_oneshot = timed(lambda: apsp.solve_batched(work))
+    same_oneshot = all(torch.equal(a, b) for a, b in zip(ref, work))
+    info = plan.info()
+    plan.close()
+
+    def loop():
+        for w_ in work:
+            apsp.solve(w_)
+
+    t_loop = timed(loop)
+    same = same_oneshot and all(torch.equal(a, b) for a, b in zip(ref, work))
+    log(f"batched: plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches), one-shot "
+        f"call {t_oneshot * 1e3:.2f} ms, per-graph loop {t_loop * 1e3:.2f} ms, identical={same}")
+    return {"workload": f"{count} ER graphs, n log-uniform [32,512], p=8/n, int32 U{{1..1000}}; "
+                        "row length rounded up to 4 elements",
+            "sum_n3": sum_n3, "batched_ms": round(t_batched * 1e3, 3),
+            "plan": info, "oneshot_call_ms": round(t_oneshot * 1e3, 3),
+            "plain_loop_ms": round(t_loop * 1e3, 3),
+            "batched_T_cell_updates_per_s": round(sum_n3 / t_batched / 1e12, 3),
+            "plain_loop_T_cell_updates_per_s": round(sum_n3 / t_loop / 1e12, 3),
+            "speedup": round(t_loop / t_batched, 2), "bit_identical": bool(same)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--batched", type=int, default=4096,
+                    help="graphs in the batched-vs-plain comparison (0 disables it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
     args = ap.parse_args()
@@ -218,6 +280,10 @@ def main() -> int:
         "avg_launch_ms": round(launch_s * 1e3, 4),
     }
 
+    batched = None
+    if args.batched > 0:
+        batched = bench_batched(apsp, torch, dev, args.batched, reps=3)
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(n, u, v, w, args.cpu_seconds)
@@ -242,6 +308,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "valu_probe": probe,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -118,13 +118,17 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
 int32_t apsp_round_width(int64_t n, int32_t dtype);
 
 /*
- * apsp_solve_batched -- solve `count` independent int32 graphs in one launch.
+ * apsp_solve_batched -- solve `count` independent int32 graphs together.
  *   ptrs[g]  device pointer to graph g's n_g x n_g int32 matrix (ld = n_g),
  *            solved in place; graphs must not overlap in memory.
  *   ns[g]    n_g, 0 <= n_g <= APSP_BATCHED_MAX_N.
  *   count    number of graphs, >= 0 (0: no-op; ptrs/ns may then be NULL).
- * Each graph gets exactly the result apsp_solve would give it (int32 is
- * exact).  Allocates a small stream-ordered device descriptor table.
+ * Every graph goes through the rounds of the blocked method (Sec. 4.4/4.5)
+ * with round width apsp_batched_round_width(); each launch covers one phase
+ * of one round for all graphs (1 + 2 * max_g ceil(n_g/b) launches).  int32
+ * results are exactly apsp_solve's.  Builds a one-shot plan: its tables are
+ * copied to stream-ordered device memory (hipMallocAsync) and freed
+ * stream-ordered after the launches.
  * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY or
  * APSP_ERR_DEVICE.
  */
@@ -134,14 +138,36 @@ int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, 
 /*
  * apsp_solve_batched_ex -- as apsp_solve_batched with per-graph leading
  * dimensions (lds[g] >= max(n_g, 1); lds == NULL means ld = n) and a dtype
- * for the whole batch.  fp32 graphs are solved with the batched round width
- * (apsp_batched_round_width), so their last bits may differ from apsp_solve;
- * both are the blocked method in IEEE fp32.
+ * for the whole batch.  fp32 graphs use the batched round width, so their
+ * last bits may differ from apsp_solve's when that width differs; both are
+ * the blocked method in IEEE fp32.
  */
 int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_t *lds,
                               int32_t count, int32_t dtype, void *stream);
 
-/* Round width used inside the batched kernel for a graph of n vertices. */
+/*
+ * Reusable batched plans.  apsp_batched_plan_create checks the arguments as
+ * apsp_solve_batched_ex does, builds the descriptor and work-item tables on
+ * the host, copies them into library-owned device memory (hipMalloc) and
+ * waits for the copy on `stream`.  apsp_batched_plan_run enqueues the solve
+ * of all the plan's graphs on `stream` and allocates nothing, so it may be
+ * captured in a HIP graph; it may be called any number of times, for any
+ * matrices now stored at the plan's pointers.  apsp_batched_plan_destroy
+ * frees the tables (hipFree, which waits for the device); the caller must
+ * not destroy a plan whose runs are still pending on another stream.
+ * apsp_batched_plan_info writes {launches, work items, tile updates}.
+ * The plan keeps the matrix pointers, not the matrices: the caller keeps
+ * them allocated while the plan is used.
+ */
+typedef struct apsp_batch_plan apsp_batch_plan;
+int32_t apsp_batched_plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                 int32_t count, int32_t dtype, void *stream,
+                                 apsp_batch_plan **plan);
+int32_t apsp_batched_plan_run(const apsp_batch_plan *plan, void *stream);
+int32_t apsp_batched_plan_info(const apsp_batch_plan *plan, int64_t *info);
+int32_t apsp_batched_plan_destroy(apsp_batch_plan *plan);
+
+/* Round width used for a graph of n vertices in the batched path. */
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype);
 
 /*

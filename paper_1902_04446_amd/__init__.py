@@ -15,7 +15,8 @@ import os
 
 __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
-    "solve", "solve_profiled", "solve_rounds", "solve_batched", "validate", "round_width",
+    "solve", "solve_profiled", "solve_rounds", "solve_batched", "BatchPlan", "validate",
+    "round_width",
     "batched_round_width", "num_rounds", "version",
 ]
 
@@ -54,6 +55,10 @@ def _load() -> ctypes.CDLL:
         "apsp_solve_batched": ([vp, vp, i32, vp], i32),
         "apsp_solve_batched_ex": ([vp, vp, vp, i32, i32, vp], i32),
         "apsp_validate": ([vp, i64, i64, i32, vp], i32),
+        "apsp_batched_plan_create": ([vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "apsp_batched_plan_run": ([vp, vp], i32),
+        "apsp_batched_plan_info": ([vp, ctypes.POINTER(i64)], i32),
+        "apsp_batched_plan_destroy": ([vp], i32),
         "apsp_status_string": ([i32], ctypes.c_char_p),
         "apsp_version": ([], ctypes.c_char_p),
     }
@@ -157,33 +162,105 @@ def solve_rounds(t, r0: int, r1: int, stream=None):
     return t
 
 
+def _batch_arrays(mats):
+    """Host arrays (ptrs, ns, lds) and dtype code of a list of square device matrices."""
+    import torch
+
+    count = len(mats)
+    ptrs = (ctypes.c_void_p * count)()
+    ns = (ctypes.c_int32 * count)()
+    lds = (ctypes.c_int64 * count)()
+    if count == 0:
+        return ptrs, ns, lds, APSP_I32, None
+    dt = _dtype_code(mats[0])
+    dev = mats[0].device
+    tdt = mats[0].dtype
+    if not mats[0].is_cuda:
+        raise ValueError("the APSP library works on device (ROCm) tensors only")
+    for g, m in enumerate(mats):
+        if m.dtype != tdt:
+            raise TypeError("a batch must have a single dtype")
+        if m.device != dev:
+            raise ValueError("all matrices of a batch must be on one device")
+        shp = m.shape
+        if len(shp) != 2 or shp[0] != shp[1]:
+            raise ValueError(f"expected square 2-D matrices, got shape {tuple(shp)}")
+        n = shp[0]
+        st = m.stride()
+        if n > 1 and st[1] != 1:
+            raise ValueError("matrix columns must be contiguous (stride(1) == 1)")
+        ptrs[g] = m.data_ptr()
+        ns[g] = n
+        lds[g] = max(st[0], n, 1)
+    del torch
+    return ptrs, ns, lds, dt, dev
+
+
 def solve_batched(mats, stream=None):
-    """Solve a list of independent square matrices (all int32, or all float32) in one launch."""
+    """Solve a list of independent square matrices (all int32, or all float32) together."""
     import torch
 
     mats = list(mats)
     if not mats:
         return mats
-    codes = {_dtype_code(m) for m in mats}
-    if len(codes) != 1:
-        raise TypeError("a batch must have a single dtype")
-    dt = codes.pop()
-    count = len(mats)
-    ptrs = (ctypes.c_void_p * count)()
-    ns = (ctypes.c_int32 * count)()
-    lds = (ctypes.c_int64 * count)()
-    dev = mats[0].device
-    for g, m in enumerate(mats):
-        if m.device != dev:
-            raise ValueError("all matrices of a batch must be on one device")
-        p, n, ld, _ = _matrix_args(m)
-        ptrs[g] = p
-        ns[g] = n
-        lds[g] = ld
+    ptrs, ns, lds, dt, dev = _batch_arrays(mats)
     with torch.cuda.device(dev):
-        _check(_LIB.apsp_solve_batched_ex(ptrs, ns, lds, count, dt, _stream(stream)),
+        _check(_LIB.apsp_solve_batched_ex(ptrs, ns, lds, len(mats), dt, _stream(stream)),
                "apsp_solve_batched_ex")
     return mats
+
+
+class BatchPlan:
+    """A reusable batched solve of fixed matrices (apsp_batched_plan_*).
+
+    The descriptor and work tables live in device memory; ``run()`` only
+    enqueues kernels, so it is cheap to repeat and can be graph-captured.
+    The plan refers to the matrices' memory: keep ``mats`` alive while it is used.
+    """
+
+    def __init__(self, mats, stream=None):
+        import torch
+
+        self.mats = list(mats)
+        self._plan = ctypes.c_void_p(None)
+        ptrs, ns, lds, dt, dev = _batch_arrays(self.mats)
+        self.device = dev
+        with torch.cuda.device(dev) if dev is not None else _nullcontext():
+            _check(_LIB.apsp_batched_plan_create(ptrs, ns, lds, len(self.mats), dt,
+                                                 _stream(stream), ctypes.byref(self._plan)),
+                   "apsp_batched_plan_create")
+
+    def run(self, stream=None):
+        import torch
+
+        with torch.cuda.device(self.device) if self.device is not None else _nullcontext():
+            _check(_LIB.apsp_batched_plan_run(self._plan, _stream(stream)),
+                   "apsp_batched_plan_run")
+        return self.mats
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 3)()
+        _check(_LIB.apsp_batched_plan_info(self._plan, out), "apsp_batched_plan_info")
+        return {"launches": int(out[0]), "items": int(out[1]), "tile_updates": int(out[2])}
+
+    def close(self):
+        if self._plan:
+            _LIB.apsp_batched_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _nullcontext:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *exc):
+        return False
 
 
 def validate(t, stream=None) -> bool:

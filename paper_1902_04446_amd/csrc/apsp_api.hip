@@ -1,14 +1,11 @@
 // C ABI of the APSP library (declared in include/apsp.h).  Arguments are
 // checked on the host before any HIP call; kernels are enqueued on the
 // caller's stream; nothing here blocks except apsp_validate.
-#include <algorithm>
-#include <numeric>
 #include <vector>
 
 #include "../../include/apsp.h"
 #include "apsp_common.h"
 
-using apsp::BatchDesc;
 
 namespace {
 
@@ -70,59 +67,6 @@ int32_t apsp_round_width(int64_t, int32_t dtype) {
 
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype) {
     return bad_dtype(dtype) ? 0 : apsp::batched_tile(n);
-}
-
-int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_t *lds,
-                              int32_t count, int32_t dtype, void *stream) {
-    if (bad_dtype(dtype) || count < 0) return APSP_ERR_INVALID_VALUE;
-    if (count == 0) return APSP_OK;
-    if (ptrs == nullptr || ns == nullptr) return APSP_ERR_INVALID_VALUE;
-    int max_n = 0;
-    for (int32_t g = 0; g < count; ++g) {
-        const int64_t n = ns[g];
-        const int64_t ld = lds ? lds[g] : (n > 1 ? n : 1);
-        if (n < 0 || n > APSP_BATCHED_MAX_N) return APSP_ERR_INVALID_VALUE;
-        if (ld < (n > 1 ? n : 1)) return APSP_ERR_INVALID_VALUE;
-        if (n > 0 && ptrs[g] == nullptr) return APSP_ERR_INVALID_VALUE;
-        max_n = std::max<int>(max_n, (int)n);
-    }
-    // Longest job first: the hardware dispatches workgroups in order.
-    std::vector<int32_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return ns[a] > ns[b]; });
-    std::vector<BatchDesc> host;
-    host.reserve(count);
-    for (int32_t g : order) {
-        if (ns[g] == 0) continue;
-        BatchDesc d;
-        d.ptr = static_cast<uint32_t *>(ptrs[g]);
-        d.ld = lds ? lds[g] : (ns[g] > 1 ? ns[g] : 1);
-        d.n = ns[g];
-        d.pad_ = 0;
-        host.push_back(d);
-    }
-    if (host.empty()) return APSP_OK;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    void *dev = nullptr;
-    const size_t bytes = host.size() * sizeof(BatchDesc);
-    if (hipMallocAsync(&dev, bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return APSP_ERR_NO_MEMORY;
-    }
-    // Pageable source: the copy has consumed `host` when the call returns.
-    if (hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
-        (void)hipFreeAsync(dev, s);
-        return APSP_ERR_DEVICE;
-    }
-    const hipError_t e = apsp::launch_batched(static_cast<const BatchDesc *>(dev),
-                                              (int32_t)host.size(), max_n, dtype, s);
-    if (hipFreeAsync(dev, s) != hipSuccess || e != hipSuccess) return APSP_ERR_DEVICE;
-    return APSP_OK;
-}
-
-int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, void *stream) {
-    return apsp_solve_batched_ex(ptrs, ns, nullptr, count, APSP_I32, stream);
 }
 
 int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {

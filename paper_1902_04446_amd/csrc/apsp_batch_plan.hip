@@ -1,0 +1,274 @@
+// Batched-solve plans: the per-graph descriptors and the per-launch work
+// items of the round-synchronous batched schedule (see apsp_batched.hip),
+// built on the host once and kept in device memory, so running a plan is
+// nothing but kernel launches (and can be captured in a HIP graph).
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/apsp.h"
+#include "apsp_common.h"
+
+struct apsp_batch_plan {
+    int dtype = 0;
+    int device = 0;
+    bool stream_ordered = false;  // buffers from hipMallocAsync (one-shot plans)
+    apsp::BatchDesc *d_descs = nullptr;
+    apsp::BatchItem *d_items = nullptr;
+    struct Launch {
+        int r;
+        bool close_only;
+        apsp::XcdRanges ranges;
+    };
+    std::vector<Launch> launches;
+    int64_t items = 0;
+    int64_t tiles = 0;  // tile updates (phase 2/3 items), for reporting
+};
+
+namespace apsp {
+
+namespace {
+
+constexpr int kB = kRoundB;
+
+int rounds_of(int n) { return (n + kB - 1) / kB; }
+
+}  // namespace
+
+// Build the plan's host tables; returns APSP_OK or APSP_ERR_INVALID_VALUE.
+int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                   int32_t count, std::vector<BatchDesc> &descs, std::vector<BatchItem> &items) {
+    descs.clear();
+    items.clear();
+    for (int32_t g = 0; g < count; ++g) {
+        if (ns[g] == 0) continue;
+        BatchDesc d;
+        d.ptr = static_cast<uint32_t *>(ptrs[g]);
+        d.ld = lds ? lds[g] : (ns[g] > 1 ? ns[g] : 1);
+        d.n = ns[g];
+        d.pad_ = 0;
+        descs.push_back(d);
+    }
+    const int G = (int)descs.size();
+    if (G == 0) return APSP_OK;
+    // Balance graphs over the 8 XCDs by tile work (longest first, least
+    // loaded XCD), so each XCD's item list of every launch is about as long.
+    std::vector<int> order(G), xcd(G, 0);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return descs[a].n > descs[b].n; });
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g : order) {
+        const double q = rounds_of(descs[g].n);
+        const int best = (int)(std::min_element(load, load + 8) - load);
+        xcd[g] = best;
+        load[best] += q * q * q;
+    }
+    int qmax = 0;
+    for (const auto &d : descs) qmax = std::max(qmax, rounds_of(d.n));
+
+    std::vector<BatchItem> per[8];
+    auto flush = [&](int r, bool close_only) {
+        apsp_batch_plan::Launch L;
+        L.r = r;
+        L.close_only = close_only;
+        for (int x = 0; x < 8; ++x) {
+            L.ranges.offset[x] = (int32_t)items.size();
+            L.ranges.count[x] = (int32_t)per[x].size();
+            items.insert(items.end(), per[x].begin(), per[x].end());
+            per[x].clear();
+        }
+        p.launches.push_back(L);
+    };
+    auto push = [&](int g, int I, int J) {
+        BatchItem it;
+        it.graph = g;
+        it.ij = (I << 16) | J;
+        per[xcd[g]].push_back(it);
+    };
+    // launch 0: phase 1 of round 0, every graph
+    for (int g : order) push(g, 0, 0);
+    flush(0, true);
+    for (int r = 0; r < qmax; ++r) {
+        for (int g : order) {  // phase 2 of round r
+            const int q = rounds_of(descs[g].n);
+            if (q <= r || q == 1) continue;
+            for (int J = 0; J < q; ++J)
+                if (J != r) push(g, r, J);
+            for (int I = 0; I < q; ++I)
+                if (I != r) push(g, I, r);
+        }
+        flush(r, false);
+        // phase 3 of round r.  The workgroup of diagonal block r+1 also
+        // closes it, so it runs about twice as long: those items go first,
+        // where they overlap the rest of the launch instead of its tail.
+        for (int g : order) {
+            const int q = rounds_of(descs[g].n);
+            if (q <= r || q == 1) continue;
+            if (r + 1 < q) push(g, r + 1, r + 1);
+        }
+        for (int g : order) {
+            const int q = rounds_of(descs[g].n);
+            if (q <= r || q == 1) continue;
+            for (int I = 0; I < q; ++I)
+                for (int J = 0; J < q; ++J)
+                    if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
+        }
+        flush(r, false);
+    }
+    p.items = (int64_t)items.size();
+    p.tiles = p.items - G;
+    return APSP_OK;
+}
+
+}  // namespace apsp
+
+namespace {
+
+bool bad_dtype(int32_t dtype) { return dtype != APSP_I32 && dtype != APSP_F32; }
+
+int32_t check_batch(void *const *ptrs, const int32_t *ns, const int64_t *lds, int32_t count,
+                    int32_t dtype) {
+    if (bad_dtype(dtype) || count < 0) return APSP_ERR_INVALID_VALUE;
+    if (count == 0) return APSP_OK;
+    if (ptrs == nullptr || ns == nullptr) return APSP_ERR_INVALID_VALUE;
+    for (int32_t g = 0; g < count; ++g) {
+        const int64_t n = ns[g];
+        const int64_t ld = lds ? lds[g] : (n > 1 ? n : 1);
+        if (n < 0 || n > APSP_BATCHED_MAX_N) return APSP_ERR_INVALID_VALUE;
+        if (ld < (n > 1 ? n : 1)) return APSP_ERR_INVALID_VALUE;
+        if (n > 0 && ptrs[g] == nullptr) return APSP_ERR_INVALID_VALUE;
+    }
+    return APSP_OK;
+}
+
+void free_plan_buffers(apsp_batch_plan *p, hipStream_t s) {
+    if (p->stream_ordered) {
+        if (p->d_descs) (void)hipFreeAsync(p->d_descs, s);
+        if (p->d_items) (void)hipFreeAsync(p->d_items, s);
+    } else {
+        if (p->d_descs) (void)hipFree(p->d_descs);
+        if (p->d_items) (void)hipFree(p->d_items);
+    }
+    p->d_descs = nullptr;
+    p->d_items = nullptr;
+}
+
+// Create a plan; `stream_ordered` selects hipMallocAsync on `s` (one-shot use)
+// instead of hipMalloc.
+int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, int32_t count,
+                    int32_t dtype, hipStream_t s, bool stream_ordered, apsp_batch_plan **out) {
+    *out = nullptr;
+    const int32_t st = check_batch(ptrs, ns, lds, count, dtype);
+    if (st != APSP_OK) return st;
+    apsp_batch_plan *p = new (std::nothrow) apsp_batch_plan();
+    if (!p) return APSP_ERR_NO_MEMORY;
+    p->dtype = dtype;
+    p->stream_ordered = stream_ordered;
+    p->device = -1;
+    std::vector<apsp::BatchDesc> descs;
+    std::vector<apsp::BatchItem> items;
+    if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, descs, items);
+    if (!descs.empty()) {  // an empty batch makes no HIP call at all
+        if (hipGetDevice(&p->device) != hipSuccess) {
+            delete p;
+            return APSP_ERR_DEVICE;
+        }
+        const size_t db = descs.size() * sizeof(apsp::BatchDesc);
+        const size_t ib = items.size() * sizeof(apsp::BatchItem);
+        hipError_t e1, e2;
+        if (stream_ordered) {
+            e1 = hipMallocAsync(reinterpret_cast<void **>(&p->d_descs), db, s);
+            e2 = hipMallocAsync(reinterpret_cast<void **>(&p->d_items), ib, s);
+        } else {
+            e1 = hipMalloc(reinterpret_cast<void **>(&p->d_descs), db);
+            e2 = hipMalloc(reinterpret_cast<void **>(&p->d_items), ib);
+        }
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            (void)hipGetLastError();
+            free_plan_buffers(p, s);
+            delete p;
+            return APSP_ERR_NO_MEMORY;
+        }
+        // Pageable sources: both copies have consumed the host vectors when
+        // they return.
+        if (hipMemcpyAsync(p->d_descs, descs.data(), db, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(p->d_items, items.data(), ib, hipMemcpyHostToDevice, s) != hipSuccess) {
+            free_plan_buffers(p, s);
+            delete p;
+            return APSP_ERR_DEVICE;
+        }
+        if (!stream_ordered && hipStreamSynchronize(s) != hipSuccess) {
+            free_plan_buffers(p, s);
+            delete p;
+            return APSP_ERR_DEVICE;
+        }
+    }
+    *out = p;
+    return APSP_OK;
+}
+
+int32_t plan_run(const apsp_batch_plan *p, hipStream_t s) {
+    for (const auto &L : p->launches)
+        if (apsp::launch_batched_items(p->d_descs, p->d_items, L.ranges, L.r, L.close_only,
+                                       p->dtype, s) != hipSuccess)
+            return APSP_ERR_DEVICE;
+    return APSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t apsp_batched_plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                 int32_t count, int32_t dtype, void *stream,
+                                 apsp_batch_plan **plan) {
+    if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
+    return plan_create(ptrs, ns, lds, count, dtype, reinterpret_cast<hipStream_t>(stream), false,
+                       plan);
+}
+
+int32_t apsp_batched_plan_run(const apsp_batch_plan *plan, void *stream) {
+    if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
+    return plan_run(plan, reinterpret_cast<hipStream_t>(stream));
+}
+
+int32_t apsp_batched_plan_info(const apsp_batch_plan *plan, int64_t *info) {
+    if (plan == nullptr || info == nullptr) return APSP_ERR_INVALID_VALUE;
+    info[0] = (int64_t)plan->launches.size();
+    info[1] = plan->items;
+    info[2] = plan->tiles;
+    return APSP_OK;
+}
+
+int32_t apsp_batched_plan_destroy(apsp_batch_plan *plan) {
+    if (plan == nullptr) return APSP_OK;
+    if (plan->device >= 0) {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (have && cur != plan->device) (void)hipSetDevice(plan->device);
+        free_plan_buffers(plan, nullptr);
+        if (have && cur != plan->device) (void)hipSetDevice(cur);
+    }
+    delete plan;
+    return APSP_OK;
+}
+
+int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                              int32_t count, int32_t dtype, void *stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    apsp_batch_plan *p = nullptr;
+    const int32_t st = plan_create(ptrs, ns, lds, count, dtype, s, true, &p);
+    if (st != APSP_OK) return st;
+    const int32_t rs = plan_run(p, s);
+    free_plan_buffers(p, s);  // stream-ordered: freed after the launches
+    delete p;
+    return rs;
+}
+
+int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, void *stream) {
+    return apsp_solve_batched_ex(ptrs, ns, nullptr, count, APSP_I32, stream);
+}
+
+}  // extern "C"

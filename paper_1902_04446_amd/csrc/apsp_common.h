@@ -32,6 +32,8 @@ struct OpI32 {
         return min2(min2(a, b), c);
     }
     static __device__ __forceinline__ uint32_t pad() { return kInfI32; }
+    // input normalisation: anything above 2^30 means "no edge"
+    static __device__ __forceinline__ uint32_t norm(uint32_t v) { return v > kInfI32 ? kInfI32 : v; }
 };
 
 struct OpF32 {
@@ -45,6 +47,7 @@ struct OpF32 {
         return min2(min2(a, b), c);
     }
     static __device__ __forceinline__ uint32_t pad() { return kInfF32Bits; }
+    static __device__ __forceinline__ uint32_t norm(uint32_t v) { return v; }
 };
 
 // Round width of the single-graph solver and the output tile of the
@@ -57,6 +60,20 @@ struct BatchDesc {
     int64_t ld;
     int32_t n;
     int32_t pad_;
+};
+
+// One workgroup's work in a batched launch: tile (I, J) = (ij >> 16, ij & 0xffff)
+// of graph `graph`.
+struct BatchItem {
+    int32_t graph;
+    int32_t ij;
+};
+
+// Items of a batched launch, grouped by the XCD their workgroups run on
+// (workgroup w runs on XCD w % 8): XCD x takes items offset[x] .. +count[x].
+struct XcdRanges {
+    int32_t offset[8];
+    int32_t count[8];
 };
 
 // Tile sets of the min-plus tile kernel (round r, q rounds):
@@ -76,8 +93,9 @@ int64_t num_rounds(int64_t n);
 int64_t tile_count(int64_t n, int64_t r, int set);
 hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,
                            hipStream_t s);
-hipError_t launch_batched(const BatchDesc *descs_dev, int32_t count, int max_n, int dtype,
-                          hipStream_t s);
+hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
+                                const XcdRanges &ranges, int r, bool close_only, int dtype,
+                                hipStream_t s);
 int batched_tile(int64_t n);
 
 // ---- round scheduler (apsp_runtime.hip) ------------------------------------

@@ -1,0 +1,263 @@
+// Device building blocks shared by the single-graph and batched solvers: a
+// 128 x 128 register-blocked min-plus tile update (arXiv:1902.04446, Table 1
+// MinPlus = MatProd then MatMin) and the Floyd-Warshall closure of a
+// diagonal block held in the same register layout (Table 1 FloydWarshall).
+//
+// Register layout of a 128 x 128 tile over 256 threads: thread (tx, ty) =
+// (t % 16, t / 16) holds acc[m][e] = C[row(m)][col(e)] with
+// row(m) = (m / 4) * 64 + ty * 4 + m % 4 and col(e) = (e / 4) * 64 + tx * 4 + e % 4.
+#pragma once
+
+#include "apsp_common.h"
+
+namespace apsp {
+namespace tile {
+
+constexpr int TB = kRoundB;  // tile edge == round width
+constexpr int KC = 16;       // k values per LDS stage
+constexpr int NT = 256;      // threads per tile workgroup
+
+// LDS of one tile workgroup: two stages of the column-panel operand, stored
+// as k-pairs (a[i][k], a[i][k+1]), and of the row-panel operand.
+struct Lds {
+    uint2 As[2][KC / 2][TB];
+    uint4 Bs[2][KC][TB / 4];
+};
+
+__device__ __forceinline__ uint4 ld4(const uint32_t *p) {
+    return *reinterpret_cast<const uint4 *>(p);
+}
+__device__ __forceinline__ void st4(uint32_t *p, uint4 v) { *reinterpret_cast<uint4 *>(p) = v; }
+
+__device__ __forceinline__ int row_of(int m, int ty) { return (m >> 2) * 64 + ty * 4 + (m & 3); }
+__device__ __forceinline__ int col_of(int e, int tx) { return (e >> 2) * 64 + tx * 4 + (e & 3); }
+
+// Load the mr x nc tile at (i0, j0) into acc; entries outside are padded with
+// "no edge".  NORM applies the input normalisation on the way in (int32
+// values above 2^30 -> 2^30; a tile on the diagonal gets a zero diagonal).
+template <class Op, bool NORM>
+__device__ __forceinline__ void load_acc(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
+                                         int64_t i0, int64_t j0, int mr, int nc, bool vec) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const uint32_t PAD = Op::pad();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int row = row_of(m, ty);
+        const uint32_t *crow = D + (i0 + (row < mr ? row : mr - 1)) * ld + j0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int col = h * 64 + tx * 4;
+            if (vec && row < mr && col + 3 < nc) {
+                const uint4 c4 = ld4(crow + col);
+                acc[m][h * 4 + 0] = c4.x;
+                acc[m][h * 4 + 1] = c4.y;
+                acc[m][h * 4 + 2] = c4.z;
+                acc[m][h * 4 + 3] = c4.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t x = crow[col + e < nc ? col + e : nc - 1];
+                    acc[m][h * 4 + e] = (row < mr && col + e < nc) ? x : PAD;
+                }
+            }
+        }
+    }
+    if (NORM) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[m][e] = Op::norm(acc[m][e]);
+        if (i0 == j0) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (row_of(m, ty) == col_of(e, tx)) acc[m][e] = 0u;
+        }
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t *D, int64_t ld,
+                                          int64_t i0, int64_t j0, int mr, int nc, bool vec) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int row = row_of(m, ty);
+        if (row >= mr) continue;
+        uint32_t *crow = D + (i0 + row) * ld + j0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int col = h * 64 + tx * 4;
+            if (vec && col + 3 < nc) {
+                st4(crow + col, make_uint4(acc[m][h * 4 + 0], acc[m][h * 4 + 1],
+                                           acc[m][h * 4 + 2], acc[m][h * 4 + 3]));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (col + e < nc) crow[col + e] = acc[m][h * 4 + e];
+            }
+        }
+    }
+}
+
+// acc = min(acc, A (x) B) with A = D[i0 .. i0+mr, kb .. kb+kw) and
+// B = D[kb .. kb+kw, j0 .. j0+nc).  k runs in stages of 16 through
+// double-buffered LDS, prefetched into registers one stage ahead; one
+// barrier per stage; every thread returns after a final barrier, so the LDS
+// may be reused at once.  One min3 folds the two candidates of a k-pair:
+//     c = min3(c, a[i][k] + b[k][j], a[i][k+1] + b[k+1][j])
+// (2 adds + 1 min3 per 2 updates).  Out-of-range rows, columns and k read
+// as "no edge", which never wins a minimum.  The operands are read from
+// global memory only, so C may be one of them as long as it is stored after
+// this returns (phase 2).
+template <class Op, bool NORM>
+__device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
+                                             int64_t i0, int64_t j0, int64_t kb, int mr, int nc,
+                                             int kw, bool vec, Lds &L) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const uint32_t PAD = Op::pad();
+    const int ar = t >> 1, ak = (t & 1) * 8;   // A: row ar, k offset ak..ak+7 of a stage
+    const int br = t >> 4, bc = (t & 15) * 8;  // B: k row br of a stage, columns bc..bc+7
+    const uint32_t *Arow = D + (i0 + (ar < mr ? ar : mr - 1)) * ld + kb;
+    const uint32_t *Bbase = D + kb * ld + j0;
+
+    uint32_t pa[8], pb[8];
+    auto gload = [&](int c) {
+        const int kk = c * KC + ak;
+        if (vec && ar < mr && kk + 8 <= kw) {
+            const uint4 x0 = ld4(Arow + kk), x1 = ld4(Arow + kk + 4);
+            pa[0] = x0.x; pa[1] = x0.y; pa[2] = x0.z; pa[3] = x0.w;
+            pa[4] = x1.x; pa[5] = x1.y; pa[6] = x1.z; pa[7] = x1.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t x = Arow[kk + e < kw ? kk + e : kw - 1];
+                pa[e] = (ar < mr && kk + e < kw) ? x : PAD;
+            }
+        }
+        const int kr = c * KC + br;
+        const uint32_t *brow = Bbase + (int64_t)(kr < kw ? kr : kw - 1) * ld;
+        if (vec && kr < kw && bc + 8 <= nc) {
+            const uint4 y0 = ld4(brow + bc), y1 = ld4(brow + bc + 4);
+            pb[0] = y0.x; pb[1] = y0.y; pb[2] = y0.z; pb[3] = y0.w;
+            pb[4] = y1.x; pb[5] = y1.y; pb[6] = y1.z; pb[7] = y1.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t x = brow[bc + e < nc ? bc + e : nc - 1];
+                pb[e] = (kr < kw && bc + e < nc) ? x : PAD;
+            }
+        }
+        if (NORM) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                pa[e] = Op::norm(pa[e]);
+                pb[e] = Op::norm(pb[e]);
+            }
+        }
+    };
+    auto sstore = [&](int s) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            L.As[s][(ak >> 1) + p][ar] = make_uint2(pa[2 * p], pa[2 * p + 1]);
+        L.Bs[s][br][(bc >> 2) + 0] = make_uint4(pb[0], pb[1], pb[2], pb[3]);
+        L.Bs[s][br][(bc >> 2) + 1] = make_uint4(pb[4], pb[5], pb[6], pb[7]);
+    };
+
+    const int nch = (kw + KC - 1) / KC;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int s = c & 1;
+        if (c + 1 < nch) gload(c + 1);
+#pragma unroll 2
+        for (int p = 0; p < KC / 2; ++p) {
+            uint32_t a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const uint2 av = L.As[s][p][row_of(m, ty)];
+                a0[m] = av.x;
+                a1[m] = av.y;
+            }
+            const uint4 b00 = L.Bs[s][2 * p][tx], b01 = L.Bs[s][2 * p][16 + tx];
+            const uint4 b10 = L.Bs[s][2 * p + 1][tx], b11 = L.Bs[s][2 * p + 1][16 + tx];
+            b0[0] = b00.x; b0[1] = b00.y; b0[2] = b00.z; b0[3] = b00.w;
+            b0[4] = b01.x; b0[5] = b01.y; b0[6] = b01.z; b0[7] = b01.w;
+            b1[0] = b10.x; b1[1] = b10.y; b1[2] = b10.z; b1[3] = b10.w;
+            b1[4] = b11.x; b1[5] = b11.y; b1[6] = b11.z; b1[7] = b11.w;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+        }
+        if (c + 1 < nch) sstore(s ^ 1);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Floyd-Warshall closure of a (kw x kw, kw <= 128) diagonal block held in
+// registers in the layout of k_tiles (thread (tx, ty) holds rows
+// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).  Pivot k:
+// the 16 threads holding row k and the 16 holding column k publish them to
+// LDS (double-buffered, one barrier per pivot), then every thread applies
+// d_ij = min(d_ij, d_ik + d_kj) to its 64 entries.  Same operations in the
+// same order as the textbook loop, so the same bits.  `lds` needs 4 x 128 words
+// and every thread returns after the last pivot's barrier.
+// ---------------------------------------------------------------------------
+template <class Op>
+__device__ __forceinline__ void close_block(uint32_t (&acc)[8][8], int kw, uint32_t *lds) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    uint32_t *rowbuf = lds;            // [2][128]
+    uint32_t *colbuf = lds + 2 * TB;   // [2][128]
+    // pivots in ascending order: k = kh*64 + kq*4 + u
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+        for (int kq = 0; kq < 16; ++kq) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kh * 64 + kq * 4 + u;
+                if (k < kw) {
+                    const int sel = (k & 1) * TB;
+                    const int mk = kh * 4 + u;  // register row/column index of pivot k
+                    if (ty == kq) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&rowbuf[sel + h * 64 + tx * 4]) =
+                                make_uint4(acc[mk][h * 4 + 0], acc[mk][h * 4 + 1],
+                                           acc[mk][h * 4 + 2], acc[mk][h * 4 + 3]);
+                    }
+                    if (tx == kq) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&colbuf[sel + h * 64 + ty * 4]) =
+                                make_uint4(acc[h * 4 + 0][mk], acc[h * 4 + 1][mk],
+                                           acc[h * 4 + 2][mk], acc[h * 4 + 3][mk]);
+                    }
+                    __syncthreads();
+                    uint32_t dik[8], dkj[8];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint4 c4 = *reinterpret_cast<const uint4 *>(&colbuf[sel + h * 64 + ty * 4]);
+                        const uint4 r4 = *reinterpret_cast<const uint4 *>(&rowbuf[sel + h * 64 + tx * 4]);
+                        dik[h * 4 + 0] = c4.x; dik[h * 4 + 1] = c4.y;
+                        dik[h * 4 + 2] = c4.z; dik[h * 4 + 3] = c4.w;
+                        dkj[h * 4 + 0] = r4.x; dkj[h * 4 + 1] = r4.y;
+                        dkj[h * 4 + 2] = r4.z; dkj[h * 4 + 3] = r4.w;
+                    }
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            acc[m][e] = Op::min2(acc[m][e], Op::add(dik[m], dkj[e]));
+                }
+            }
+        }
+    }
+}
+
+}  // namespace tile
+}  // namespace apsp

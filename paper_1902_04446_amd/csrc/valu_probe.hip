@@ -65,7 +65,7 @@ int apsp_probe_valu_rates(double *rates) {
     const int grid = cus * 32;  // 32 workgroups of 4 waves per CU: every SIMD saturated
     uint32_t *out = nullptr;
     if (hipMalloc(&out, sizeof(uint32_t) * (size_t)grid * 256) != hipSuccess) return -1;
-    const int iters = 4000;
+    const int iters = 20000;
     rates[0] = rate<0>(out, grid, iters);
     rates[1] = rate<1>(out, grid, iters);
     rates[2] = rate<2>(out, grid, iters);

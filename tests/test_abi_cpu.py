@@ -92,6 +92,27 @@ def test_batched_argument_validation(lib):
     assert lib.apsp_solve_batched(null_ptrs, zero_n, 2, None) == 0  # all empty: no-op
 
 
+def test_batched_plan_argument_validation(lib):
+    vp = ctypes.c_void_p
+    plan = vp(None)
+    ns = (ctypes.c_int32 * 2)(4, 5)
+    ptrs = (vp * 2)(0x1000, 0x2000)
+    assert lib.apsp_batched_plan_create(ptrs, ns, None, 2, 0, None, None) == 1
+    assert lib.apsp_batched_plan_create(ptrs, ns, None, -1, 0, None, ctypes.byref(plan)) == 1
+    assert lib.apsp_batched_plan_create(None, ns, None, 2, 0, None, ctypes.byref(plan)) == 1
+    assert lib.apsp_batched_plan_create(ptrs, ns, None, 2, 3, None, ctypes.byref(plan)) == 1
+    assert not plan
+    # an empty batch needs no device at all
+    assert lib.apsp_batched_plan_create(None, None, None, 0, 0, None, ctypes.byref(plan)) == 0
+    assert plan
+    info = (ctypes.c_int64 * 3)()
+    assert lib.apsp_batched_plan_info(plan, info) == 0 and list(info) == [0, 0, 0]
+    assert lib.apsp_batched_plan_run(plan, None) == 0
+    assert lib.apsp_batched_plan_destroy(plan) == 0
+    assert lib.apsp_batched_plan_run(None, None) == 1
+    assert lib.apsp_batched_plan_destroy(None) == 0
+
+
 def test_status_strings_and_widths(lib):
     for code in range(6):
         s = lib.apsp_status_string(code)
@@ -99,7 +120,7 @@ def test_status_strings_and_widths(lib):
     assert lib.apsp_status_string(99) == b"APSP: unknown status"
     assert lib.apsp_round_width(100, 0) == 128 and lib.apsp_round_width(100, 1) == 128
     assert lib.apsp_round_width(100, 5) == 0
-    assert lib.apsp_batched_round_width(300, 0) == 64
+    assert lib.apsp_batched_round_width(300, 0) == 128
     assert b"gfx950" in lib.apsp_version()
 
 

@@ -335,3 +335,24 @@ def test_batched_config_4096_graphs(apsp, dev):
     sample = gg.rng_for(gg.CFG_TEST, 4096).choice(len(Ws), size=96, replace=False)
     for g in sample:
         assert np.array_equal(views[g].cpu().numpy().astype(np.int64), oracle.fw(Ws[g])), g
+
+
+def test_batched_plan_reuse(apsp, dev):
+    """A plan is built once and run repeatedly on fresh inputs at the same pointers."""
+    import torch
+
+    sizes = [1, 40, 128, 129, 300, 512]
+    Ws = [_er(n, min(1.0, 8.0 / n), 700 + n, 1, 1000)[0] for n in sizes]
+    mats = [torch.from_numpy(W).to(dev) for W in Ws]
+    plan = apsp.BatchPlan(mats)
+    info = plan.info()
+    # launches: phase 1 of round 0, then phases 2 and 3 of each of the 4 rounds
+    assert info["launches"] == 1 + 2 * 4
+    for rep in range(2):
+        for m, W in zip(mats, Ws):
+            m.copy_(torch.from_numpy(W).to(dev))
+        plan.run()
+        torch.cuda.synchronize()
+        for m, W in zip(mats, Ws):
+            assert np.array_equal(m.cpu().numpy().astype(np.int64), oracle.fw(W)), (rep, W.shape)
+    plan.close()
