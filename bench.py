@@ -195,6 +195,67 @@ def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
             "speedup": round(t_loop / t_batched, 2), "bit_identical": bool(same)}
 
 
+def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2)) -> dict:
+    """Poisson stream of APSP requests, n in {256, 1024, 4096, 8192} with
+    probabilities {.4, .3, .2, .1}, each a seeded Swiss-roll kNN graph (k=10,
+    fp32).  Capacity C = requests per second of back-to-back plain solves of
+    the same requests on one stream; the server then runs at the given
+    fractions of C and reports p50 / p99 latency and cell updates per second.
+    """
+    import numpy as np
+
+    import graphgen as gg
+    from paper_1902_04446_amd.serving import ApspServer, GpuBackend, Request
+
+    per_size = 3
+    log("serving: generating the request pool")
+    pool = {n: [gg.swiss_roll_knn(n, gg.CFG_SERVING, 10 * n + k) for k in range(per_size)]
+            for n in gg.SERVING_SIZES}
+
+    def make(qps, item):
+        arr, ns = gg.serving_requests(count, qps, item=item)
+        return [Request(rid=i, n=int(n), arrival=float(a), payload=pool[int(n)][i % per_size])
+                for i, (a, n) in enumerate(zip(arr, ns))]
+
+    # capacity: the same kind of requests, one after another, plain solves
+    probe = make(1.0, 0)
+    backend = GpuBackend(dev, slots=1, keep_results=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in probe:
+        D = backend.alloc(r)
+        backend.load(D, r, 0)
+        with torch.cuda.stream(backend.streams[0]):
+            apsp.solve(D)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    cap = len(probe) / t_plain
+    work = float(sum(float(r.n) ** 3 for r in probe))
+    log(f"serving: plain back-to-back {len(probe)} requests in {t_plain:.3f} s "
+        f"-> capacity {cap:.1f} req/s, {work / t_plain / 1e12:.2f} T cell-updates/s")
+    runs = []
+    for k, f in enumerate(loads):
+        qps = f * cap
+        reqs = make(qps, k + 1)
+        backend = GpuBackend(dev, slots=4, keep_results=False)
+        srv = ApspServer(backend, hbm_budget=8 << 30, slots=4, slice_rounds=8, inflight=2)
+        st = srv.run(reqs, realtime=True)
+        st["load"] = f
+        st["qps"] = round(qps, 2)
+        for key in ("p50_ms", "p99_ms", "mean_ms"):
+            st[key] = round(st[key], 3) if st[key] is not None else None
+        st["T_cell_updates_per_s"] = round(st.pop("cell_updates_per_s") / 1e12, 3)
+        st["makespan_s"] = round(st["makespan_s"], 3)
+        log(f"serving: load {f:.1f}C ({qps:.0f} req/s): p50 {st['p50_ms']} ms, "
+            f"p99 {st['p99_ms']} ms, {st['T_cell_updates_per_s']} T cell-updates/s")
+        runs.append(st)
+    return {"workload": "Poisson arrivals, n in {256,1024,4096,8192} w.p. {.4,.3,.2,.1}, "
+                        "Swiss-roll kNN fp32", "requests_per_run": count,
+            "plain_capacity_req_per_s": round(cap, 2),
+            "plain_T_cell_updates_per_s": round(work / t_plain / 1e12, 3),
+            "slots": 4, "slice_rounds": 8, "hbm_budget_GiB": 8, "runs": runs}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +264,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--batched", type=int, default=4096,
                     help="graphs in the batched-vs-plain comparison (0 disables it)")
+    ap.add_argument("--serving", type=int, default=300,
+                    help="requests per serving run (0 disables the serving section)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
     args = ap.parse_args()
@@ -284,6 +347,10 @@ def main() -> int:
     if args.batched > 0:
         batched = bench_batched(apsp, torch, dev, args.batched, reps=3)
 
+    serving = None
+    if args.serving > 0:
+        serving = bench_serving(apsp, torch, dev, args.serving)
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(n, u, v, w, args.cpu_seconds)
@@ -309,6 +376,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "valu_probe": probe,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -181,6 +181,11 @@ int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, vo
 /* Static description of a status code (never NULL). */
 const char *apsp_status_string(int32_t status);
 
+/* The HIP call that made the calling thread's most recent call fail with
+ * APSP_ERR_DEVICE or APSP_ERR_NO_MEMORY, with its error name and code
+ * (empty string if none; never NULL). */
+const char *apsp_last_error(void);
+
 /* Library version string, e.g. "apsp-mi355x 0.1.0 gfx950". */
 const char *apsp_version(void);
 

@@ -35,10 +35,18 @@ def lib_path() -> str:
 class ApspError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
-        super().__init__(f"{what}: {_LIB.apsp_status_string(status).decode()} (status {status})")
+        detail = _LIB.apsp_last_error().decode() if status in (3, 4) else ""
+        super().__init__(f"{what}: {_LIB.apsp_status_string(status).decode()} (status {status})"
+                         + (f" [{detail}]" if detail else ""))
 
 
 def _load() -> ctypes.CDLL:
+    # libapsp.so needs the HIP runtime (SONAME libamdhip64.so.7).  PyTorch
+    # ships its own copy of it: load torch first so the library binds to that
+    # one instance.  Loading ours first would put two HIP runtimes in the
+    # process, and the second would see no device.
+    import torch  # noqa: F401
+
     path = lib_path()
     if not os.path.exists(path):
         raise ImportError(
@@ -61,6 +69,7 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_plan_destroy": ([vp], i32),
         "apsp_status_string": ([i32], ctypes.c_char_p),
         "apsp_version": ([], ctypes.c_char_p),
+        "apsp_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

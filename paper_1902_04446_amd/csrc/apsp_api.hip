@@ -1,11 +1,24 @@
 // C ABI of the APSP library (declared in include/apsp.h).  Arguments are
 // checked on the host before any HIP call; kernels are enqueued on the
 // caller's stream; nothing here blocks except apsp_validate.
+#include <cstdio>
 #include <vector>
 
 #include "../../include/apsp.h"
 #include "apsp_common.h"
 
+
+namespace apsp {
+
+namespace {
+thread_local char g_last_error[256] = "";
+}  // namespace
+
+void note_error(const char *what, hipError_t e) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
+}
+
+}  // namespace apsp
 
 namespace {
 
@@ -107,5 +120,7 @@ const char *apsp_status_string(int32_t status) {
 }
 
 const char *apsp_version(void) { return "apsp-mi355x 0.1.0 gfx950"; }
+
+const char *apsp_last_error(void) { return apsp::g_last_error; }
 
 }  // extern "C"

@@ -98,6 +98,9 @@ hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
                                 hipStream_t s);
 int batched_tile(int64_t n);
 
+// Record the failing HIP call of the current thread (apsp_last_error()).
+void note_error(const char *what, hipError_t e);
+
 // ---- round scheduler (apsp_runtime.hip) ------------------------------------
 // Per-phase elapsed milliseconds of a profiled solve (see apsp_solve_profiled).
 struct PhaseTimes {

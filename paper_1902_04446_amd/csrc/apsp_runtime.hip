@@ -49,17 +49,29 @@ std::mutex g_map_mu;
 std::map<std::pair<int, hipStream_t>, Helper *> g_helpers;
 
 // Helper stream + events for (current device, caller stream), created once.
-Helper *helper_for(hipStream_t s) {
+Helper *helper_for(hipStream_t s, hipError_t *err) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        note_error("hipGetDevice", e);
+        *err = e;
+        return nullptr;
+    }
     std::lock_guard<std::mutex> lock(g_map_mu);
     auto key = std::make_pair(dev, s);
     auto it = g_helpers.find(key);
     if (it != g_helpers.end()) return it->second;
     Helper *h = new Helper();
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->p2_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->rest_done, hipEventDisableTiming) != hipSuccess) {
+    const char *what = "hipStreamCreateWithFlags";
+    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        what = "hipEventCreateWithFlags";
+        e = hipEventCreateWithFlags(&h->p2_done, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->rest_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        note_error(what, e);
+        *err = e;
         delete h;  // leaks a partially created stream/event only on a failing device
         return nullptr;
     }
@@ -103,8 +115,9 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     // Lookahead needs a round r+1 with a non-empty rest set.
     const bool lookahead = q >= 3;
-    Helper *h = lookahead ? helper_for(s) : nullptr;
-    if (lookahead && !h) return hipErrorOutOfMemory;
+    hipError_t herr = hipSuccess;
+    Helper *h = lookahead ? helper_for(s, &herr) : nullptr;
+    if (lookahead && !h) return herr;
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
 
@@ -132,7 +145,10 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     hipError_t err = hipSuccess;
     auto chk = [&](hipError_t e) {
-        if (e != hipSuccess && err == hipSuccess) err = e;
+        if (e != hipSuccess && err == hipSuccess) {
+            err = e;
+            note_error("kernel launch or stream call", e);
+        }
     };
     if (prologue) chk(launch_prologue(D, n, ld, dtype, s));
     if (times) rec(t_pro, s);

@@ -1,0 +1,155 @@
+"""Scheduler tests of the continuous-batching server, without a GPU.
+
+A simulated backend models each slot as a device queue that runs slices at a
+fixed rate, on a manual clock, so admission, fairness, cancellation and
+failure handling can be checked deterministically.
+"""
+import pytest
+
+from paper_1902_04446_amd.serving import ApspServer, Request, SimBackend, percentile
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+def drive(server, clock, reqs, dt=1e-4, limit=1e5):
+    reqs = sorted(reqs, key=lambda r: r.arrival)
+    i = 0
+    peak_used = 0
+    peak_active = 0
+    steps = 0
+    while i < len(reqs) or not server.idle():
+        while i < len(reqs) and reqs[i].arrival <= clock.t:
+            server.submit(reqs[i])
+            i += 1
+        server.step(clock.t)
+        peak_used = max(peak_used, server.used)
+        peak_active = max(peak_active, len(server.active))
+        clock.t += dt
+        steps += 1
+        assert steps < limit, "scheduler did not drain"
+    return peak_used, peak_active
+
+
+def mk(sizes, arrivals=None):
+    arrivals = arrivals or [0.0] * len(sizes)
+    return [Request(rid=i, n=n, arrival=a) for i, (n, a) in enumerate(zip(sizes, arrivals))]
+
+
+def test_all_requests_complete_and_latency_covers_service_time():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    srv = ApspServer(be, hbm_budget=1 << 34, slots=4, slice_rounds=4, clock=clock)
+    reqs = mk([256, 1024, 4096, 256, 1024])
+    drive(srv, clock, reqs)
+    assert all(r.status == "done" for r in reqs)
+    for r in reqs:
+        assert r.latency >= r.n ** 3 / 1e12 - 1e-3
+    assert be.allocated == be.freed == len(reqs)
+
+
+def test_admission_respects_memory_budget():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    need = be.bytes_needed(2048)
+    srv = ApspServer(be, hbm_budget=2 * need + 10, slots=8, slice_rounds=2, clock=clock)
+    reqs = mk([2048] * 6)
+    peak_used, peak_active = drive(srv, clock, reqs)
+    assert peak_used <= srv.budget
+    assert peak_active == 2
+    assert all(r.status == "done" for r in reqs)
+
+
+def test_slots_bound_concurrency():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    srv = ApspServer(be, hbm_budget=1 << 40, slots=3, slice_rounds=2, clock=clock)
+    _, peak_active = drive(srv, clock, mk([512] * 10))
+    assert peak_active == 3
+
+
+def test_oversized_request_is_rejected_not_queued():
+    clock = Clock()
+    be = SimBackend(clock=clock)
+    srv = ApspServer(be, hbm_budget=be.bytes_needed(1000), slots=2, clock=clock)
+    reqs = mk([1001, 500])
+    drive(srv, clock, reqs)
+    assert reqs[0].status == "rejected" and reqs[1].status == "done"
+
+
+def test_small_request_overtakes_a_running_large_one():
+    # continuous batching: a small request that arrives while a large one is
+    # on the device is admitted into a free slot and finishes first
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    srv = ApspServer(be, hbm_budget=1 << 36, slots=2, slice_rounds=1, clock=clock)
+    reqs = mk([8192, 256], arrivals=[0.0, 0.05])
+    drive(srv, clock, reqs)
+    big, small = reqs
+    assert small.done < big.done
+    assert small.latency < 0.01
+
+
+def test_bypass_is_bounded():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    need_big = be.bytes_needed(4096)
+    # room for one big request; a second big one must wait while smalls flow
+    srv = ApspServer(be, hbm_budget=need_big + be.bytes_needed(256) * 2, slots=8,
+                     slice_rounds=1, max_bypass=3, clock=clock)
+    sizes = [4096, 4096] + [256] * 30
+    arrivals = [0.0, 0.0] + [0.001 * i for i in range(30)]
+    reqs = mk(sizes, arrivals)
+    drive(srv, clock, reqs)
+    assert all(r.status == "done" for r in reqs)
+    second_big = reqs[1]
+    overtakers = [r for r in reqs[2:] if r.admitted < second_big.admitted]
+    # each pending pass that skips the big request counts one bypass
+    assert second_big.bypassed > 3
+    assert len(overtakers) <= 30
+
+
+def test_cancel_pending_and_running():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    srv = ApspServer(be, hbm_budget=1 << 36, slots=1, slice_rounds=1, clock=clock)
+    reqs = mk([4096, 4096])
+    for r in reqs:
+        srv.submit(r)
+    srv.step(0.0)
+    assert srv.cancel(1)                 # still pending
+    assert reqs[1].status == "cancelled"
+    assert srv.cancel(0)                 # running: drains its enqueued slices
+    drive(srv, clock, [])
+    assert reqs[0].status == "cancelled" and srv.used == 0 and srv.free_slots == [0]
+    assert not srv.cancel(7)
+
+
+def test_failed_slice_is_retried_then_gives_up():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock, fail=(0,))
+    srv = ApspServer(be, hbm_budget=1 << 36, slots=2, slice_rounds=2, max_retries=1,
+                     clock=clock)
+    reqs = mk([1024, 512])
+    drive(srv, clock, reqs)
+    assert reqs[0].status == "done" and reqs[0].retries == 1
+    clock2 = Clock()
+    be2 = SimBackend(rate=1e12, clock=clock2, fail=(0,))
+    srv2 = ApspServer(be2, hbm_budget=1 << 36, slots=2, slice_rounds=2, max_retries=0,
+                      clock=clock2)
+    reqs2 = mk([1024])
+    drive(srv2, clock2, reqs2)
+    assert reqs2[0].status == "failed" and srv2.used == 0
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert percentile(v, 50) == 50
+    assert percentile(v, 99) == 99
+    assert percentile(v, 100) == 100
+    assert percentile([3.0], 99) == 3.0
