@@ -171,6 +171,37 @@ int32_t apsp_batched_plan_destroy(apsp_batch_plan *plan);
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype);
 
 /*
+ * apsp_minplus -- min-plus product (Table 1: MatProd; with accumulate,
+ * MinPlus = MatProd followed by MatMin):
+ *   accumulate == 0:  C = A (x) B,          C_ij = min_k A_ik + B_kj
+ *   accumulate != 0:  C = min(C, A (x) B)
+ * C is m x n, A is m x k, B is k x n, all row-major device matrices of one
+ * dtype with leading dimensions ldc >= n, lda >= k, ldb >= n.  k >= 1 (k == 0
+ * is APSP_ERR_INVALID_VALUE); m == 0 or n == 0 is a no-op.  C must not
+ * overlap A or B (checked on the address ranges; APSP_ERR_INVALID_VALUE).
+ * Entries follow the matrix format above ("no edge" = 2^30 / +inf, values
+ * >= 0); int32 sums of two entries <= 2^30 cannot wrap (computed as uint32).
+ * Asynchronous on `stream`; allocates nothing.
+ */
+int32_t apsp_minplus(void *C, int64_t ldc, const void *A, int64_t lda, const void *B, int64_t ldb,
+                     int64_t m, int64_t n, int64_t k, int32_t dtype, int32_t accumulate,
+                     void *stream);
+
+/*
+ * apsp_solve_squaring -- APSP by repeated min-plus squaring (Sec. 4.2,
+ * Algorithm 1): after input normalisation, X <- X (x) X is applied
+ * apsp_squarings(n) = ceil(log2(n - 1)) times (n >= 3; 0 otherwise), which
+ * covers every path of up to n - 1 edges.  `work` is a caller-provided
+ * n x n device buffer (leading dimension ldw >= n) that must not overlap
+ * `dist`; the result ends in `dist`.  Does ceil(log2(n-1)) times the work of
+ * apsp_solve; int32 results are identical to it, fp32 results differ in
+ * summation order only.  Asynchronous; allocates nothing.
+ */
+int32_t apsp_solve_squaring(void *dist, int64_t n, int64_t ld, int32_t dtype, void *work,
+                            int64_t ldw, void *stream);
+int32_t apsp_squarings(int64_t n);
+
+/*
  * apsp_validate -- check the input domain (Sec. 3: non-negative weights, no
  * NaN) of an n x n matrix.  Synchronous: waits on `stream` for its own result.
  * Returns APSP_OK when every entry is >= 0 (and not NaN), APSP_ERR_BAD_INPUT

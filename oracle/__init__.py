@@ -23,6 +23,7 @@ Functions:
 ``blocked``        three-phase blocked method, Sec. 4.4/4.5, Alg. 3/4, in the
                    element type the device computes in (uint32 or fp32)
 ``minplus_acc``    Table 1 MinPlus: C = min(C, A (x) B)
+``squaring``       repeated min-plus squaring, Sec. 4.2, Alg. 1
 ``bellman_*``      Bellman optimality certificate over chosen rows
 """
 from __future__ import annotations
@@ -63,6 +64,8 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
         "orc_minplus_acc_f32": ([_p, _i64, _p, _i64, _p, _i64, _i64, _i64, _i64], None),
         "orc_minplus_acc_u32": ([_p, _i64, _p, _i64, _p, _i64, _i64, _i64, _i64], None),
         "orc_blocked_u32": ([_p, _i64, _i64, _i64, _i64], None),
+        "orc_squaring_u32": ([_p, _i64, _i64], None),
+        "orc_squaring_f32": ([_p, _i64, _i64], None),
         "orc_blocked_f32": ([_p, _i64, _i64, _i64, _i64], None),
         "orc_bellman_residual_f32": ([_p, _i64, _i64, _p, _p, _p, _p, _i64, ctypes.c_int],
                                      ctypes.c_double),
@@ -231,6 +234,36 @@ def blocked(W: np.ndarray, b: int, r0: int = 0, r1: int | None = None) -> np.nda
         lib.orc_blocked_f32(_ptr(D), n, b, r0, r1)
         return D
     raise TypeError("blocked takes int32 or float32")
+
+
+def squaring_steps(n: int) -> int:
+    """Squarings that cover every path of up to n - 1 edges: ceil(log2(n - 1))."""
+    s = 0
+    while n > 2 and (1 << s) < n - 1:
+        s += 1
+    return s
+
+
+def squaring(W: np.ndarray, steps: int | None = None) -> np.ndarray:
+    """Repeated min-plus squaring (Sec. 4.2, Alg. 1) in the device element type.
+
+    int32 in -> int32 out (computed as uint32); float32 in -> float32 out.
+    """
+    lib = _lib()
+    W = np.asarray(W)
+    n = W.shape[0]
+    steps = squaring_steps(n) if steps is None else steps
+    if W.dtype == np.int32:
+        X = prepare(np.ascontiguousarray(W)).astype(np.uint32)
+        lib.orc_squaring_u32(_ptr(X), n, steps)
+        return X.astype(np.int32)
+    if W.dtype == np.float32:
+        X = np.ascontiguousarray(W).copy()
+        if n:
+            np.fill_diagonal(X, 0.0)
+        lib.orc_squaring_f32(_ptr(X), n, steps)
+        return X
+    raise TypeError("squaring takes int32 or float32")
 
 
 def minplus_acc(C: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:

@@ -37,6 +37,8 @@
  *                             device path, with phase products taken on the
  *                             values before the phase starts
  *   orc_minplus_*             the min-plus product of Table 1 (MatProd)
+ *   orc_squaring_*            repeated min-plus squaring (Sec. 4.2,
+ *                             Algorithm 1) in the device element type
  *   orc_bellman_*             Bellman optimality residual, a certificate that
  *                             characterises the distance matrix when w > 0
  *
@@ -350,6 +352,39 @@ void orc_minplus_acc_u32(const uint32_t *A, int64_t lda, const uint32_t *B, int6
             }
             C[i * ldc + j] = best;
         }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Repeated squaring (Sec. 4.2, Algorithm 1): X <- X (x) X, `steps` times,  */
+/* on a prepared n x n matrix (diagonal 0).  Each product is taken whole    */
+/* into a temporary (every entry from the same X), then copied back.        */
+/* ------------------------------------------------------------------------ */
+#define ORC_SQUARING_BODY(T)                                                    \
+    T *Y = (T *)malloc(sizeof(T) * (size_t)(n * n + 1));                       \
+    for (int64_t st = 0; st < steps; ++st) {                                   \
+        for (int64_t i = 0; i < n; ++i)                                        \
+            for (int64_t j = 0; j < n; ++j) {                                  \
+                T best = X[i * n + 0] + X[0 * n + j];                          \
+                for (int64_t k = 1; k < n; ++k) {                              \
+                    const T c = X[i * n + k] + X[k * n + j];                   \
+                    if (c < best) best = c;                                    \
+                }                                                              \
+                Y[i * n + j] = best;                                           \
+            }                                                                  \
+        memcpy(X, Y, sizeof(T) * (size_t)(n * n));                             \
+    }                                                                          \
+    free(Y);
+
+void orc_squaring_u32(uint32_t *X, int64_t n, int64_t steps)
+{
+    if (n < 1) return;
+    ORC_SQUARING_BODY(uint32_t)
+}
+
+void orc_squaring_f32(float *X, int64_t n, int64_t steps)
+{
+    if (n < 1) return;
+    ORC_SQUARING_BODY(float)
 }
 
 /* ------------------------------------------------------------------------ */

@@ -16,6 +16,7 @@ import os
 __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
     "solve", "solve_profiled", "solve_rounds", "solve_batched", "BatchPlan", "validate",
+    "minplus", "solve_squaring", "squarings",
     "round_width",
     "batched_round_width", "num_rounds", "version",
 ]
@@ -69,6 +70,9 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_plan_destroy": ([vp], i32),
         "apsp_status_string": ([i32], ctypes.c_char_p),
         "apsp_version": ([], ctypes.c_char_p),
+        "apsp_minplus": ([vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp], i32),
+        "apsp_solve_squaring": ([vp, i64, i64, i32, vp, i64, vp], i32),
+        "apsp_squarings": ([i64], i32),
         "apsp_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
@@ -270,6 +274,42 @@ class _nullcontext:
 
     def __exit__(self, *exc):
         return False
+
+
+def minplus(C, A, B, accumulate: bool = False, stream=None):
+    """C = A (x) B (min-plus product), or C = min(C, A (x) B) with accumulate.  In place on C."""
+    for name, t in (("C", C), ("A", A), ("B", B)):
+        if not t.is_cuda or t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+            raise ValueError(f"{name} must be a 2-D device matrix with contiguous rows")
+    if not (C.dtype == A.dtype == B.dtype):
+        raise TypeError("C, A and B must have one dtype")
+    m, k = A.shape
+    k2, n = B.shape
+    if k != k2 or tuple(C.shape) != (m, n):
+        raise ValueError(f"shape mismatch: C {tuple(C.shape)}, A {tuple(A.shape)}, B {tuple(B.shape)}")
+    dt = _dtype_code(C)
+    ld = lambda t: max(int(t.stride(0)), int(t.shape[1]), 1)  # noqa: E731
+    with _device_of(C):
+        _check(_LIB.apsp_minplus(ctypes.c_void_p(C.data_ptr()), ld(C), ctypes.c_void_p(A.data_ptr()),
+                                 ld(A), ctypes.c_void_p(B.data_ptr()), ld(B), m, n, k, dt,
+                                 1 if accumulate else 0, _stream(stream)), "apsp_minplus")
+    return C
+
+
+def squarings(n: int) -> int:
+    return int(_LIB.apsp_squarings(n))
+
+
+def solve_squaring(t, work, stream=None):
+    """APSP by repeated min-plus squaring (Sec. 4.2); ``work`` is an n x n scratch matrix."""
+    ptr, n, ld, dt = _matrix_args(t)
+    wptr, wn, wld, wdt = _matrix_args(work)
+    if wn != n or wdt != dt:
+        raise ValueError("work must be an n x n matrix of the same dtype")
+    with _device_of(t):
+        _check(_LIB.apsp_solve_squaring(ctypes.c_void_p(ptr), n, ld, dt, ctypes.c_void_p(wptr), wld,
+                                        _stream(stream)), "apsp_solve_squaring")
+    return t
 
 
 def validate(t, stream=None) -> bool:

@@ -2,6 +2,7 @@
 // checked on the host before any HIP call; kernels are enqueued on the
 // caller's stream; nothing here blocks except apsp_validate.
 #include <cstdio>
+#include <utility>
 #include <vector>
 
 #include "../../include/apsp.h"
@@ -80,6 +81,77 @@ int32_t apsp_round_width(int64_t, int32_t dtype) {
 
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype) {
     return bad_dtype(dtype) ? 0 : apsp::batched_tile(n);
+}
+
+int32_t apsp_minplus(void *C, int64_t ldc, const void *A, int64_t lda, const void *B, int64_t ldb,
+                     int64_t m, int64_t n, int64_t k, int32_t dtype, int32_t accumulate,
+                     void *stream) {
+    if (bad_dtype(dtype) || m < 0 || n < 0 || k < 0) return APSP_ERR_INVALID_VALUE;
+    if (m == 0 || n == 0) return APSP_OK;
+    if (k == 0 || k >= kMaxN) return APSP_ERR_INVALID_VALUE;
+    if (!C || !A || !B) return APSP_ERR_INVALID_VALUE;
+    if (ldc < n || lda < k || ldb < n) return APSP_ERR_INVALID_VALUE;
+    const int64_t tiles = ((m + apsp::kRoundB - 1) / apsp::kRoundB) *
+                          ((n + apsp::kRoundB - 1) / apsp::kRoundB);
+    if (tiles >= kMaxN) return APSP_ERR_INVALID_VALUE;
+    // C must not overlap an operand: compare the address ranges spanned
+    const uintptr_t c0 = reinterpret_cast<uintptr_t>(C);
+    const uintptr_t c1 = c0 + 4 * (uintptr_t)((m - 1) * ldc + n);
+    auto overlaps = [&](const void *p, int64_t rows, int64_t ld, int64_t cols) {
+        const uintptr_t p0 = reinterpret_cast<uintptr_t>(p);
+        const uintptr_t p1 = p0 + 4 * (uintptr_t)((rows - 1) * ld + cols);
+        return p0 < c1 && c0 < p1;
+    };
+    if (overlaps(A, m, lda, k) || overlaps(B, k, ldb, n)) return APSP_ERR_INVALID_VALUE;
+    const hipError_t e = apsp::launch_minplus(
+        static_cast<uint32_t *>(C), ldc, static_cast<const uint32_t *>(A), lda,
+        static_cast<const uint32_t *>(B), ldb, m, n, k, dtype, accumulate != 0,
+        reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        apsp::note_error("min-plus product launch", e);
+        return APSP_ERR_DEVICE;
+    }
+    return APSP_OK;
+}
+
+int32_t apsp_squarings(int64_t n) {
+    int32_t s = 0;
+    while (n > 2 && ((int64_t)1 << s) < n - 1) ++s;
+    return s;
+}
+
+int32_t apsp_solve_squaring(void *dist, int64_t n, int64_t ld, int32_t dtype, void *work,
+                            int64_t ldw, void *stream) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    if (n == 0) return APSP_OK;
+    if (work == nullptr || ldw < n) return APSP_ERR_INVALID_VALUE;
+    {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(dist);
+        const uintptr_t a1 = a0 + 4 * (uintptr_t)((n - 1) * ld + n);
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(work);
+        const uintptr_t b1 = b0 + 4 * (uintptr_t)((n - 1) * ldw + n);
+        if (a0 < b1 && b0 < a1) return APSP_ERR_INVALID_VALUE;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t *X = static_cast<uint32_t *>(dist), *Y = static_cast<uint32_t *>(work);
+    int64_t ldx = ld, ldy = ldw;
+    hipError_t e = apsp::launch_prologue(X, n, ld, dtype, s);
+    const int32_t steps = apsp_squarings(n);
+    for (int32_t i = 0; i < steps && e == hipSuccess; ++i) {
+        // with a zero diagonal X (x) X <= X, so the product alone is the update
+        e = apsp::launch_minplus(Y, ldy, X, ldx, X, ldx, n, n, n, dtype, false, s);
+        std::swap(X, Y);
+        std::swap(ldx, ldy);
+    }
+    if (e == hipSuccess && X != static_cast<uint32_t *>(dist))
+        e = hipMemcpy2DAsync(dist, (size_t)ld * 4, X, (size_t)ldx * 4, (size_t)n * 4, (size_t)n,
+                             hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        apsp::note_error("repeated squaring", e);
+        return APSP_ERR_DEVICE;
+    }
+    return APSP_OK;
 }
 
 int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {

@@ -98,6 +98,13 @@ hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
                                 hipStream_t s);
 int batched_tile(int64_t n);
 
+// C = A (x) B, or C = min(C, A (x) B) when accumulate; C is m x n, A m x k,
+// B k x n, row-major with the given leading dimensions; C must not overlap
+// A or B.  k == 0 gives "no edge" everywhere (or leaves C as it is).
+hipError_t launch_minplus(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t lda,
+                          const uint32_t *B, int64_t ldb, int64_t m, int64_t n, int64_t k,
+                          int dtype, bool accumulate, hipStream_t s);
+
 // Record the failing HIP call of the current thread (apsp_last_error()).
 void note_error(const char *what, hipError_t e);
 

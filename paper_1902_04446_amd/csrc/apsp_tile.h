@@ -101,26 +101,30 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t 
     }
 }
 
-// acc = min(acc, A (x) B) with A = D[i0 .. i0+mr, kb .. kb+kw) and
-// B = D[kb .. kb+kw, j0 .. j0+nc).  k runs in stages of 16 through
-// double-buffered LDS, prefetched into registers one stage ahead; one
-// barrier per stage; every thread returns after a final barrier, so the LDS
-// may be reused at once.  One min3 folds the two candidates of a k-pair:
+// acc = min(acc, A (x) B) for the output tile of rows i0 .. i0+mr and
+// columns j0 .. j0+nc, with A[i][k] = A[(i0 + i) * lda + k] and
+// B[k][j] = B[k * ldb + j0 + j], k in [0, kw) (any kw >= 1).  k runs in
+// stages of 16 through double-buffered LDS, prefetched into registers one
+// stage ahead; one barrier per stage; every thread returns after a final
+// barrier, so the LDS may be reused at once.  One min3 folds the two
+// candidates of a k-pair:
 //     c = min3(c, a[i][k] + b[k][j], a[i][k+1] + b[k+1][j])
 // (2 adds + 1 min3 per 2 updates).  Out-of-range rows, columns and k read
 // as "no edge", which never wins a minimum.  The operands are read from
 // global memory only, so C may be one of them as long as it is stored after
-// this returns (phase 2).
+// this returns (phase 2).  `vec` promises 16-byte aligned rows of A and B.
 template <class Op, bool NORM>
-__device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
-                                             int64_t i0, int64_t j0, int64_t kb, int mr, int nc,
-                                             int kw, bool vec, Lds &L) {
+__device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uint32_t *A, int64_t lda,
+                                                const uint32_t *B, int64_t ldb, int64_t i0,
+                                                int64_t j0, int mr, int nc, int kw, bool vec,
+                                                Lds &L) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const uint32_t PAD = Op::pad();
     const int ar = t >> 1, ak = (t & 1) * 8;   // A: row ar, k offset ak..ak+7 of a stage
     const int br = t >> 4, bc = (t & 15) * 8;  // B: k row br of a stage, columns bc..bc+7
-    const uint32_t *Arow = D + (i0 + (ar < mr ? ar : mr - 1)) * ld + kb;
-    const uint32_t *Bbase = D + kb * ld + j0;
+    const uint32_t *Arow = A + (i0 + (ar < mr ? ar : mr - 1)) * lda;
+    const uint32_t *Bbase = B + j0;
+    const int64_t ld = ldb;
 
     uint32_t pa[8], pb[8];
     auto gload = [&](int c) {
@@ -196,6 +200,14 @@ __device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32
         if (c + 1 < nch) sstore(s ^ 1);
         __syncthreads();
     }
+}
+
+// The blocked method's form: A = D[i0.., kb .. kb+kw), B = D[kb .. kb+kw, j0..].
+template <class Op, bool NORM>
+__device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
+                                             int64_t i0, int64_t j0, int64_t kb, int mr, int nc,
+                                             int kw, bool vec, Lds &L) {
+    minplus_tile_ab<Op, NORM>(acc, D + kb, ld, D + kb * ld, ld, i0, j0, mr, nc, kw, vec, L);
 }
 
 // ---------------------------------------------------------------------------

@@ -113,6 +113,26 @@ def test_batched_plan_argument_validation(lib):
     assert lib.apsp_batched_plan_destroy(None) == 0
 
 
+def test_minplus_and_squaring_argument_validation(lib):
+    vp = ctypes.c_void_p
+    a, b, c = vp(0x10000), vp(0x80000), vp(0x100000)
+    assert lib.apsp_minplus(c, 8, a, 8, b, 8, 8, 8, 8, 5, 0, None) == 1       # dtype
+    assert lib.apsp_minplus(c, 8, a, 8, b, 8, 8, 8, 0, 0, 0, None) == 1       # k == 0
+    assert lib.apsp_minplus(c, 8, a, 8, b, 8, 0, 8, 8, 0, 0, None) == 0       # m == 0: no-op
+    assert lib.apsp_minplus(c, 7, a, 8, b, 8, 8, 8, 8, 0, 0, None) == 1       # ldc < n
+    assert lib.apsp_minplus(c, 8, a, 7, b, 8, 8, 8, 8, 0, 0, None) == 1       # lda < k
+    assert lib.apsp_minplus(None, 8, a, 8, b, 8, 8, 8, 8, 0, 0, None) == 1
+    assert lib.apsp_minplus(a, 8, a, 8, b, 8, 8, 8, 8, 0, 0, None) == 1       # C overlaps A
+    assert lib.apsp_minplus(vp(0x80000 + 64), 8, a, 8, b, 8, 8, 8, 8, 0, 0, None) == 1  # C in B
+    assert lib.apsp_squarings(0) == 0 and lib.apsp_squarings(2) == 0
+    assert lib.apsp_squarings(3) == 1 and lib.apsp_squarings(5) == 2 and lib.apsp_squarings(6) == 3
+    assert lib.apsp_squarings(16385) == 14
+    assert lib.apsp_solve_squaring(a, 8, 8, 0, None, 8, None) == 1           # no work buffer
+    assert lib.apsp_solve_squaring(a, 8, 8, 0, vp(0x10000 + 16), 8, None) == 1  # overlapping
+    assert lib.apsp_solve_squaring(a, 8, 8, 0, b, 7, None) == 1              # ldw < n
+    assert lib.apsp_solve_squaring(None, 0, 1, 0, None, 1, None) == 0
+
+
 def test_status_strings_and_widths(lib):
     for code in range(6):
         s = lib.apsp_status_string(code)

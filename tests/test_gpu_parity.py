@@ -356,3 +356,64 @@ def test_batched_plan_reuse(apsp, dev):
         for m, W in zip(mats, Ws):
             assert np.array_equal(m.cpu().numpy().astype(np.int64), oracle.fw(W)), (rep, W.shape)
     plan.close()
+
+
+# -------------------------------------------------- min-plus product, squaring
+
+def _rand_operand(shape, dtype, seed, p_inf=0.3):
+    rng = gg.rng_for(gg.CFG_TEST, seed)
+    if dtype == np.int32:
+        X = rng.integers(0, 1000, size=shape).astype(np.int32)
+        X[rng.random(shape) < p_inf] = INF
+    else:
+        X = (rng.random(shape) * 10).astype(np.float32)
+        X[rng.random(shape) < p_inf] = np.inf
+    return X
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 7, 3), (128, 128, 128), (130, 257, 200),
+                                   (300, 100, 513), (64, 1000, 17)])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_minplus_product(apsp, dev, dtype, m, n, k, accumulate):
+    import torch
+
+    A = _rand_operand((m, k), dtype, m * 7 + k)
+    B = _rand_operand((k, n), dtype, n * 11 + k)
+    C0 = _rand_operand((m, n), dtype, m + n)
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    # C with a padded leading dimension
+    buf = torch.full((m, n + 5), 7, dtype=tA.dtype, device=dev)
+    tC = buf[:, :n]
+    tC.copy_(torch.from_numpy(C0).to(dev))
+    apsp.minplus(tC, tA, tB, accumulate=accumulate)
+    torch.cuda.synchronize()
+    start = C0 if accumulate else np.full_like(C0, INF if dtype == np.int32 else np.inf)
+    ref = oracle.minplus_acc(start, A, B)
+    assert np.array_equal(tC.cpu().numpy(), ref)
+    assert (buf[:, n:] == 7).all()
+
+
+@pytest.mark.parametrize("n", [2, 3, 100, 300])
+def test_repeated_squaring(apsp, dev, n):
+    import torch
+
+    Wi, _ = _er(n, min(1.0, 3.0 / n), 9000 + n)
+    Wf, _ = _swiss(n, 9100 + n) if n > 11 else (np.zeros((n, n), np.float32), None)
+    for W in (Wi, Wf):
+        D = torch.from_numpy(W).to(dev)
+        work = torch.empty_like(D)
+        apsp.solve_squaring(D, work)
+        torch.cuda.synchronize()
+        got = D.cpu().numpy()
+        assert np.array_equal(got, oracle.squaring(W)), (n, W.dtype)
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W))
+
+
+def test_minplus_rejects_overlap(apsp, dev):
+    import torch
+
+    A = torch.zeros((64, 64), dtype=torch.float32, device=dev)
+    with pytest.raises(apsp.ApspError):
+        apsp.minplus(A, A, A)

@@ -243,6 +243,35 @@ def test_minplus_matches_definition():
     assert np.array_equal(oracle.minplus_acc(Ci, Ai, Bi).astype(np.int64), refi)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 9, 64, 130])
+def test_squaring_int_equals_fw(n):
+    W, _ = _rand_int_graph(n, min(1.0, 3.0 / n), 1, 100, 4000 + n)
+    assert np.array_equal(oracle.squaring(W).astype(np.int64), oracle.fw(W))
+
+
+def test_squaring_step_count_is_minimal_on_a_path():
+    # a path of n vertices needs paths of n-1 edges: ceil(log2(n-1)) squarings
+    # reach the far end, one fewer does not
+    for n in (3, 4, 5, 9, 17, 33, 70):
+        W = _path(n, 1, np.int32)
+        s = oracle.squaring_steps(n)
+        assert (1 << s) >= n - 1 and (s == 0 or (1 << (s - 1)) < n - 1)
+        assert oracle.squaring(W, s)[0, n - 1] == n - 1
+        if s:
+            assert oracle.squaring(W, s - 1)[0, n - 1] == INF
+
+
+def test_squaring_f32_within_tolerance():
+    n = 150
+    u, v, w = gg.swiss_roll_knn(n, gg.CFG_TEST, 4100)
+    W = gg.dense_from_edges(n, u, v, w, np.float32)
+    D = oracle.fw(W)
+    S = oracle.squaring(W).astype(np.float64)
+    fin = np.isfinite(D)
+    assert np.array_equal(fin, np.isfinite(S))
+    assert (np.abs(S[fin] - D[fin]) <= 1e-5 * D[fin]).all()
+
+
 # ------------------------------------------------------- invariants / Bellman
 
 def _check_invariants(W, D):
