@@ -113,6 +113,19 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
 int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream,
                             double *phase_ms);
 
+/*
+ * apsp_solve_symmetric -- apsp_solve for an undirected graph (Sec. 3:
+ * A_ij = A_ji) using only the upper-triangular blocks, as the paper stores
+ * them (Sec. 4): phases 2 and 3 update blocks (I, J) with I <= J, reading the
+ * transposes of upper blocks where the method needs a lower one; the strict
+ * lower triangle is then filled from the upper one.  Only the upper triangle
+ * of the input is read (the lower is overwritten).  For a symmetric input the
+ * result equals apsp_solve's bit for bit (fp32 addition commutes), with
+ * about half of its phase-2/3 work.  Single stream, no lookahead;
+ * asynchronous; allocates nothing.  Returns as apsp_solve.
+ */
+int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
+
 /* Round width b used by apsp_solve / apsp_solve_rounds (currently 128 for
  * every n and dtype); q = ceil(n / b) rounds.  Returns 0 for a bad dtype. */
 int32_t apsp_round_width(int64_t n, int32_t dtype);

@@ -16,7 +16,7 @@ import os
 __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
     "solve", "solve_profiled", "solve_rounds", "solve_batched", "BatchPlan", "validate",
-    "minplus", "solve_squaring", "squarings",
+    "minplus", "solve_squaring", "squarings", "solve_symmetric",
     "round_width",
     "batched_round_width", "num_rounds", "version",
 ]
@@ -73,6 +73,7 @@ def _load() -> ctypes.CDLL:
         "apsp_minplus": ([vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp], i32),
         "apsp_solve_squaring": ([vp, i64, i64, i32, vp, i64, vp], i32),
         "apsp_squarings": ([i64], i32),
+        "apsp_solve_symmetric": ([vp, i64, i64, i32, vp], i32),
         "apsp_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
@@ -147,6 +148,15 @@ def solve(t, stream=None):
     ptr, n, ld, dt = _matrix_args(t)
     with _device_of(t):
         _check(_LIB.apsp_solve(ctypes.c_void_p(ptr), n, ld, dt, _stream(stream)), "apsp_solve")
+    return t
+
+
+def solve_symmetric(t, stream=None):
+    """Solve an undirected graph's matrix in place from its upper triangle (Sec. 4 storage)."""
+    ptr, n, ld, dt = _matrix_args(t)
+    with _device_of(t):
+        _check(_LIB.apsp_solve_symmetric(ctypes.c_void_p(ptr), n, ld, dt, _stream(stream)),
+               "apsp_solve_symmetric")
     return t
 
 

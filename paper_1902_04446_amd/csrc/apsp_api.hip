@@ -154,6 +154,20 @@ int32_t apsp_solve_squaring(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
     return APSP_OK;
 }
 
+int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {
+    const int32_t st = check_matrix(dist, n, ld, dtype);
+    if (st != APSP_OK) return st;
+    if (n == 0) return APSP_OK;
+    if ((n + apsp::kRoundB - 1) / apsp::kRoundB > 46000) return APSP_ERR_INVALID_VALUE;
+    const hipError_t e = apsp::run_symmetric(static_cast<uint32_t *>(dist), n, ld, dtype,
+                                             reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        apsp::note_error("symmetric solve launch", e);
+        return APSP_ERR_DEVICE;
+    }
+    return APSP_OK;
+}
+
 int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {
     const int32_t st = check_matrix(dist, n, ld, dtype);
     if (st != APSP_OK) return st;

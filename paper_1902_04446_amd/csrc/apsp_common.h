@@ -105,6 +105,9 @@ hipError_t launch_minplus(uint32_t *C, int64_t ldc, const uint32_t *A, int64_t l
                           const uint32_t *B, int64_t ldb, int64_t m, int64_t n, int64_t k,
                           int dtype, bool accumulate, hipStream_t s);
 
+// Symmetric variant (upper-triangle blocks only, lower filled at the end).
+hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s);
+
 // Record the failing HIP call of the current thread (apsp_last_error()).
 void note_error(const char *what, hipError_t e);
 

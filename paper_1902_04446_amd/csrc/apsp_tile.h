@@ -113,44 +113,89 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t 
 // as "no edge", which never wins a minimum.  The operands are read from
 // global memory only, so C may be one of them as long as it is stored after
 // this returns (phase 2).  `vec` promises 16-byte aligned rows of A and B.
-template <class Op, bool NORM>
+//
+// TA / TB read an operand from its transpose (symmetric storage):
+//   TA: A[i][k] = A[k * lda + i0 + i]      TB: B[k][j] = B[(j0 + j) * ldb + k]
+// The transposed loaders read rows of the stored matrix (coalesced) and
+// scatter them into the same LDS layout.
+template <class Op, bool NORM, bool TA = false, bool TB = false>
 __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uint32_t *A, int64_t lda,
                                                 const uint32_t *B, int64_t ldb, int64_t i0,
                                                 int64_t j0, int mr, int nc, int kw, bool vec,
                                                 Lds &L) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const uint32_t PAD = Op::pad();
-    const int ar = t >> 1, ak = (t & 1) * 8;   // A: row ar, k offset ak..ak+7 of a stage
-    const int br = t >> 4, bc = (t & 15) * 8;  // B: k row br of a stage, columns bc..bc+7
-    const uint32_t *Arow = A + (i0 + (ar < mr ? ar : mr - 1)) * lda;
-    const uint32_t *Bbase = B + j0;
+    // direct A: row ar, k offset ak..ak+7 of a stage; transposed A: stored
+    // row (k) t/16 of a stage, columns (i) (t%16)*8 .. +7
+    const int ar = TA ? (t >> 4) : (t >> 1), ak = TA ? (t & 15) * 8 : (t & 1) * 8;
+    // direct B: k row br of a stage, columns bc..bc+7; transposed B: stored
+    // row (j) t/2, columns (k) (t%2)*8 .. +7 of a stage
+    const int br = TB ? (t >> 1) : (t >> 4), bc = TB ? (t & 1) * 8 : (t & 15) * 8;
+    const uint32_t *Arow = TA ? (A + i0) : (A + (i0 + (ar < mr ? ar : mr - 1)) * lda);
+    const uint32_t *Bbase = TB ? (B + (j0 + (br < nc ? br : nc - 1)) * ldb) : (B + j0);
     const int64_t ld = ldb;
 
     uint32_t pa[8], pb[8];
-    auto gload = [&](int c) {
-        const int kk = c * KC + ak;
-        if (vec && ar < mr && kk + 8 <= kw) {
-            const uint4 x0 = ld4(Arow + kk), x1 = ld4(Arow + kk + 4);
-            pa[0] = x0.x; pa[1] = x0.y; pa[2] = x0.z; pa[3] = x0.w;
-            pa[4] = x1.x; pa[5] = x1.y; pa[6] = x1.z; pa[7] = x1.w;
-        } else {
+    auto gload_t = [&](int c) {
+        if (TA) {  // 8 values of stored row k = c*KC + ar: A[ak .. ak+7][k]
+            const int kr = c * KC + ar;
+            const uint32_t *row = Arow + (int64_t)(kr < kw ? kr : kw - 1) * lda;
+            if (vec && kr < kw && ak + 8 <= mr) {
+                const uint4 x0 = ld4(row + ak), x1 = ld4(row + ak + 4);
+                pa[0] = x0.x; pa[1] = x0.y; pa[2] = x0.z; pa[3] = x0.w;
+                pa[4] = x1.x; pa[5] = x1.y; pa[6] = x1.z; pa[7] = x1.w;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t x = Arow[kk + e < kw ? kk + e : kw - 1];
-                pa[e] = (ar < mr && kk + e < kw) ? x : PAD;
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t x = row[ak + e < mr ? ak + e : mr - 1];
+                    pa[e] = (kr < kw && ak + e < mr) ? x : PAD;
+                }
             }
         }
-        const int kr = c * KC + br;
-        const uint32_t *brow = Bbase + (int64_t)(kr < kw ? kr : kw - 1) * ld;
-        if (vec && kr < kw && bc + 8 <= nc) {
-            const uint4 y0 = ld4(brow + bc), y1 = ld4(brow + bc + 4);
-            pb[0] = y0.x; pb[1] = y0.y; pb[2] = y0.z; pb[3] = y0.w;
-            pb[4] = y1.x; pb[5] = y1.y; pb[6] = y1.z; pb[7] = y1.w;
-        } else {
+        if (TB) {  // 8 values of stored row j = br: B[c*KC + bc .. +7][j]
+            const int kk = c * KC + bc;
+            if (vec && br < nc && kk + 8 <= kw) {
+                const uint4 y0 = ld4(Bbase + kk), y1 = ld4(Bbase + kk + 4);
+                pb[0] = y0.x; pb[1] = y0.y; pb[2] = y0.z; pb[3] = y0.w;
+                pb[4] = y1.x; pb[5] = y1.y; pb[6] = y1.z; pb[7] = y1.w;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t x = brow[bc + e < nc ? bc + e : nc - 1];
-                pb[e] = (kr < kw && bc + e < nc) ? x : PAD;
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t x = Bbase[kk + e < kw ? kk + e : kw - 1];
+                    pb[e] = (br < nc && kk + e < kw) ? x : PAD;
+                }
+            }
+        }
+    };
+    auto gload = [&](int c) {
+        gload_t(c);
+        if (!TA) {
+            const int kk = c * KC + ak;
+            if (vec && ar < mr && kk + 8 <= kw) {
+                const uint4 x0 = ld4(Arow + kk), x1 = ld4(Arow + kk + 4);
+                pa[0] = x0.x; pa[1] = x0.y; pa[2] = x0.z; pa[3] = x0.w;
+                pa[4] = x1.x; pa[5] = x1.y; pa[6] = x1.z; pa[7] = x1.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t x = Arow[kk + e < kw ? kk + e : kw - 1];
+                    pa[e] = (ar < mr && kk + e < kw) ? x : PAD;
+                }
+            }
+        }
+        if (!TB) {
+            const int kr = c * KC + br;
+            const uint32_t *brow = Bbase + (int64_t)(kr < kw ? kr : kw - 1) * ld;
+            if (vec && kr < kw && bc + 8 <= nc) {
+                const uint4 y0 = ld4(brow + bc), y1 = ld4(brow + bc + 4);
+                pb[0] = y0.x; pb[1] = y0.y; pb[2] = y0.z; pb[3] = y0.w;
+                pb[4] = y1.x; pb[5] = y1.y; pb[6] = y1.z; pb[7] = y1.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t x = brow[bc + e < nc ? bc + e : nc - 1];
+                    pb[e] = (kr < kw && bc + e < nc) ? x : PAD;
+                }
             }
         }
         if (NORM) {
@@ -162,11 +207,23 @@ __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uin
         }
     };
     auto sstore = [&](int s) {
+        if (TA) {  // element (k = ar, i = ak + e) -> word (k/2, i, k%2) of As
+            uint32_t *w = reinterpret_cast<uint32_t *>(&L.As[s][ar >> 1][0]) + (ar & 1);
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-            L.As[s][(ak >> 1) + p][ar] = make_uint2(pa[2 * p], pa[2 * p + 1]);
-        L.Bs[s][br][(bc >> 2) + 0] = make_uint4(pb[0], pb[1], pb[2], pb[3]);
-        L.Bs[s][br][(bc >> 2) + 1] = make_uint4(pb[4], pb[5], pb[6], pb[7]);
+            for (int e = 0; e < 8; ++e) w[2 * (ak + e)] = pa[e];
+        } else {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                L.As[s][(ak >> 1) + p][ar] = make_uint2(pa[2 * p], pa[2 * p + 1]);
+        }
+        if (TB) {  // element (k = bc + e, j = br) -> word j of row k of Bs
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                reinterpret_cast<uint32_t *>(&L.Bs[s][bc + e][0])[br] = pb[e];
+        } else {
+            L.Bs[s][br][(bc >> 2) + 0] = make_uint4(pb[0], pb[1], pb[2], pb[3]);
+            L.Bs[s][br][(bc >> 2) + 1] = make_uint4(pb[4], pb[5], pb[6], pb[7]);
+        }
     };
 
     const int nch = (kw + KC - 1) / KC;

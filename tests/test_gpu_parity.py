@@ -417,3 +417,24 @@ def test_minplus_rejects_overlap(apsp, dev):
     A = torch.zeros((64, 64), dtype=torch.float32, device=dev)
     with pytest.raises(apsp.ApspError):
         apsp.minplus(A, A, A)
+
+
+# ------------------------------------------------------------ symmetric variant
+
+@pytest.mark.parametrize("n", [1, 2, 100, 129, 300, 700, 1000])
+def test_symmetric_variant_equals_full_solve(apsp, dev, n):
+    """Upper-triangle solve of an undirected graph: same bits as the full solve;
+    the input's lower triangle is never read."""
+    import torch
+
+    Wi, _ = _er(n, min(1.0, 4.0 / n), 9500 + n)
+    Wf, _ = _swiss(n, 9600 + n) if n > 11 else (np.zeros((n, n), np.float32), None)
+    for W in (Wi, Wf):
+        full = _solve(apsp, W, dev)
+        junk = W.copy()
+        low = np.tril_indices(n, -1)
+        junk[low] = 3 if W.dtype == np.int32 else np.float32(0.125)
+        view, _ = _to_dev(junk, dev, ld=n + 4)
+        apsp.solve_symmetric(view)
+        torch.cuda.synchronize()
+        assert np.array_equal(view.cpu().numpy(), full), (n, W.dtype)
