@@ -256,6 +256,86 @@ def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2)) -> dict:
             "slots": 4, "slice_rounds": 8, "hbm_budget_GiB": 8, "runs": runs}
 
 
+def bench_variants(apsp, torch, dev, pristine, work, n: int, b: int) -> dict:
+    """The other solvers on the same device, measured beside the headline:
+    the symmetric (upper-triangle) variant on the same n = 16384 input, a
+    standalone 8192^3 min-plus product, and repeated squaring vs the blocked
+    method on a 4096-vertex Swiss-roll graph."""
+    import numpy as np
+
+    import graphgen as gg
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    out = {}
+    # symmetric variant: executed updates = upper panel and upper phase-3 blocks
+    def sym():
+        work.copy_(pristine)
+        apsp.solve_symmetric(work)
+
+    def full():
+        work.copy_(pristine)
+        apsp.solve(work)
+
+    t_sym, t_full = timed(sym), timed(full)
+    sym()
+    ref = work.clone()
+    full()
+    q = -(-n // b)
+    executed = sum(((q - 1) + (q - 1) * q // 2) * b ** 3 for _ in range(q)) + q * b ** 3
+    out["symmetric"] = {"n": n, "ms": round(t_sym * 1e3, 3), "full_ms": round(t_full * 1e3, 3),
+                        "T_cell_updates_per_s_n3": round(float(n) ** 3 / t_sym / 1e12, 3),
+                        "executed_updates": executed,
+                        "T_executed_updates_per_s": round(executed / t_sym / 1e12, 3),
+                        "identical_to_full": bool(torch.equal(ref, work))}
+    log(f"variants: symmetric {t_sym * 1e3:.1f} ms vs full {t_full * 1e3:.1f} ms")
+    del ref
+    # min-plus product
+    m = 8192
+    g = torch.Generator(device=dev)
+    g.manual_seed(1902)
+    A = torch.rand((m, m), device=dev, generator=g) * 10
+    B = torch.rand((m, m), device=dev, generator=g) * 10
+    C = torch.empty((m, m), device=dev)
+    t_mp = timed(lambda: apsp.minplus(C, A, B))
+    out["minplus"] = {"m": m, "n": m, "k": m, "dtype": "f32", "ms": round(t_mp * 1e3, 3),
+                      "T_cell_updates_per_s": round(float(m) ** 3 / t_mp / 1e12, 3)}
+    log(f"variants: min-plus {m}^3 in {t_mp * 1e3:.1f} ms")
+    del A, B, C
+    # repeated squaring vs blocked
+    ns = 4096
+    u, v, w = gg.swiss_roll_knn(ns, gg.CFG_TEST, 4096)
+    P = gg.device_dense_from_edges(ns, u, v, w, np.float32, dev)
+    X = torch.empty_like(P)
+    Y = torch.empty_like(P)
+
+    def squaring():
+        X.copy_(P)
+        apsp.solve_squaring(X, Y)
+
+    def blocked():
+        X.copy_(P)
+        apsp.solve(X)
+
+    t_sq, t_bl = timed(squaring), timed(blocked)
+    out["squaring"] = {"n": ns, "squarings": apsp.squarings(ns), "ms": round(t_sq * 1e3, 3),
+                       "blocked_ms": round(t_bl * 1e3, 3),
+                       "T_product_updates_per_s": round(
+                           apsp.squarings(ns) * float(ns) ** 3 / t_sq / 1e12, 3)}
+    log(f"variants: squaring n={ns} {t_sq * 1e3:.1f} ms vs blocked {t_bl * 1e3:.1f} ms")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +344,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--batched", type=int, default=4096,
                     help="graphs in the batched-vs-plain comparison (0 disables it)")
+    ap.add_argument("--variants", type=int, default=1,
+                    help="measure the symmetric, product and squaring solvers (0 disables)")
     ap.add_argument("--serving", type=int, default=300,
                     help="requests per serving run (0 disables the serving section)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -343,6 +425,10 @@ def main() -> int:
         "avg_launch_ms": round(launch_s * 1e3, 4),
     }
 
+    variants = None
+    if args.variants:
+        variants = bench_variants(apsp, torch, dev, pristine, work, n, b)
+
     batched = None
     if args.batched > 0:
         batched = bench_batched(apsp, torch, dev, args.batched, reps=3)
@@ -375,6 +461,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "valu_probe": probe,
+        "variants": variants,
         "batched": batched,
         "serving": serving,
     }
