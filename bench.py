@@ -169,11 +169,31 @@ def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
             best = min(best, time.perf_counter() - t0)
         return best
 
+    def same_as(ref):
+        return all(torch.equal(a, b) for a, b in zip(ref, work))
+
+    # fixed widths first, then the autotuned table (which plans created after
+    # the tuning pick up)
+    fixed = {}
+    ref = None
+    same = True
+    for tile in (128, 64):
+        p_ = apsp.BatchPlan(work, tile=tile)
+        fixed[tile] = (timed(p_.run), p_.info())
+        p_.close()
+        if ref is None:
+            ref = [w_.clone() for w_ in work]
+        else:
+            same = same and same_as(ref)
+    t0 = time.perf_counter()
+    tune = apsp.batched_autotune(apsp.APSP_I32, batch_elems=1 << 24)
+    t_tune = time.perf_counter() - t0
+    log(f"batched: autotuned widths {tune['widths']} in {t_tune:.2f} s")
     plan = apsp.BatchPlan(work)
     t_batched = timed(plan.run)
-    ref = [w_.clone() for w_ in work]
+    same = same and same_as(ref)
     t_oneshot = timed(lambda: apsp.solve_batched(work))
-    same_oneshot = all(torch.equal(a, b) for a, b in zip(ref, work))
+    same = same and same_as(ref)
     info = plan.info()
     plan.close()
 
@@ -182,13 +202,20 @@ def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
             apsp.solve(w_)
 
     t_loop = timed(loop)
-    same = same_oneshot and all(torch.equal(a, b) for a, b in zip(ref, work))
-    log(f"batched: plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches), one-shot "
-        f"call {t_oneshot * 1e3:.2f} ms, per-graph loop {t_loop * 1e3:.2f} ms, identical={same}")
+    same = same and same_as(ref)
+    log(f"batched: tuned plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches); "
+        f"width 128 only {fixed[128][0] * 1e3:.2f} ms, width 64 only {fixed[64][0] * 1e3:.2f} ms; "
+        f"one-shot call {t_oneshot * 1e3:.2f} ms, per-graph loop {t_loop * 1e3:.2f} ms, "
+        f"identical={same}")
     return {"workload": f"{count} ER graphs, n log-uniform [32,512], p=8/n, int32 U{{1..1000}}; "
                         "row length rounded up to 4 elements",
             "sum_n3": sum_n3, "batched_ms": round(t_batched * 1e3, 3),
-            "plan": info, "oneshot_call_ms": round(t_oneshot * 1e3, 3),
+            "plan": info, "tuned_widths": tune["widths"],
+            "autotune_ms_128_64": [[round(a, 4), round(b, 4)] for a, b in tune["ms"]],
+            "autotune_s": round(t_tune, 3),
+            "width128_only_ms": round(fixed[128][0] * 1e3, 3),
+            "width64_only_ms": round(fixed[64][0] * 1e3, 3),
+            "oneshot_call_ms": round(t_oneshot * 1e3, 3),
             "plain_loop_ms": round(t_loop * 1e3, 3),
             "batched_T_cell_updates_per_s": round(sum_n3 / t_batched / 1e12, 3),
             "plain_loop_T_cell_updates_per_s": round(sum_n3 / t_loop / 1e12, 3),

@@ -137,9 +137,10 @@ int32_t apsp_round_width(int64_t n, int32_t dtype);
  *   ns[g]    n_g, 0 <= n_g <= APSP_BATCHED_MAX_N.
  *   count    number of graphs, >= 0 (0: no-op; ptrs/ns may then be NULL).
  * Every graph goes through the rounds of the blocked method (Sec. 4.4/4.5)
- * with round width apsp_batched_round_width(); each launch covers one phase
- * of one round for all graphs (1 + 2 * max_g ceil(n_g/b) launches).  int32
- * results are exactly apsp_solve's.  Builds a one-shot plan: its tables are
+ * with round width b = apsp_batched_round_width(n_g) (64 or 128); each
+ * launch covers one phase of one round for all graphs of one width
+ * (1 + 2 * max_g ceil(n_g/b) launches per width in use).  int32 results are
+ * exactly apsp_solve's.  Builds a one-shot plan: its tables are
  * copied to stream-ordered device memory (hipMallocAsync) and freed
  * stream-ordered after the launches.
  * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY or
@@ -180,7 +181,47 @@ int32_t apsp_batched_plan_run(const apsp_batch_plan *plan, void *stream);
 int32_t apsp_batched_plan_info(const apsp_batch_plan *plan, int64_t *info);
 int32_t apsp_batched_plan_destroy(apsp_batch_plan *plan);
 
-/* Round width used for a graph of n vertices in the batched path. */
+/*
+ * apsp_batched_plan_create_tiled -- as apsp_batched_plan_create with the
+ * round width forced: tile 64 or 128 for every graph, 0 for the batched
+ * tuning table's width per graph (what apsp_batched_plan_create does).
+ * Any other tile is APSP_ERR_INVALID_VALUE.  Either width is the blocked
+ * method of Sec. 4.4/4.5 (Algorithms 3 and 4) with that block size.
+ */
+int32_t apsp_batched_plan_create_tiled(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                       int32_t count, int32_t dtype, int32_t tile, void *stream,
+                                       apsp_batch_plan **plan);
+
+/*
+ * Batched tuning table.  The batched path picks each graph's round width
+ * (64 or 128) from a per-device table of APSP_TUNE_BUCKETS size buckets:
+ * bucket b < 8 holds n in (64b, 64b + 64], bucket 8 every n > 512.  Until a
+ * device is tuned or its table is set, every bucket is 128.  Plans take the
+ * widths when they are created.
+ *   apsp_batched_tuning_get / _set  read / replace the current device's
+ *       table (count must be APSP_TUNE_BUCKETS; set accepts 64 and 128 only
+ *       and checks every entry before changing any).
+ *   apsp_batched_autotune  times both widths on the current device, bucket
+ *       by bucket, on a synthetic batch of batch_elems matrix elements
+ *       (2^20 <= batch_elems <= 2^30; graphs of the bucket's largest n, 1024
+ *       for bucket 8, back to back) and keeps 64 where it is at least 3%
+ *       faster.  It allocates batch_elems * 4 bytes (hipMalloc), runs on
+ *       `stream` and waits for it; the table is updated when every bucket
+ *       has been timed.  table (nullable) receives the widths, ms (nullable,
+ *       2 * APSP_TUNE_BUCKETS doubles) the milliseconds per run of the
+ *       128-wide and the 64-wide plan of each bucket.
+ * They return APSP_ERR_INVALID_VALUE for bad arguments and APSP_ERR_DEVICE
+ * when there is no current device.
+ */
+#define APSP_TUNE_BUCKETS 9
+int32_t apsp_batched_tuning_get(int32_t *table, int32_t count);
+int32_t apsp_batched_tuning_set(const int32_t *table, int32_t count);
+int32_t apsp_batched_autotune(int32_t dtype, int64_t batch_elems, void *stream, int32_t *table,
+                              double *ms);
+
+/* Round width (64 or 128) the batched path uses for a graph of n vertices on
+ * the current device, from the tuning table (128 without a device); 0 for a
+ * bad dtype. */
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype);
 
 /*

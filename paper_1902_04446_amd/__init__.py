@@ -17,14 +17,15 @@ __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
     "solve", "solve_profiled", "solve_rounds", "solve_batched", "BatchPlan", "validate",
     "minplus", "solve_squaring", "squarings", "solve_symmetric",
-    "round_width",
-    "batched_round_width", "num_rounds", "version",
+    "round_width", "batched_round_width", "num_rounds", "version",
+    "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
 ]
 
 APSP_I32 = 0
 APSP_F32 = 1
 INF_I32 = 1 << 30
 BATCHED_MAX_N = 4096
+TUNE_BUCKETS = 9
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -68,6 +69,12 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_plan_run": ([vp, vp], i32),
         "apsp_batched_plan_info": ([vp, ctypes.POINTER(i64)], i32),
         "apsp_batched_plan_destroy": ([vp], i32),
+        "apsp_batched_plan_create_tiled": ([vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(vp)],
+                                           i32),
+        "apsp_batched_tuning_get": ([ctypes.POINTER(i32), i32], i32),
+        "apsp_batched_tuning_set": ([ctypes.POINTER(i32), i32], i32),
+        "apsp_batched_autotune": ([i32, i64, vp, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double)], i32),
         "apsp_status_string": ([i32], ctypes.c_char_p),
         "apsp_version": ([], ctypes.c_char_p),
         "apsp_minplus": ([vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp], i32),
@@ -241,7 +248,9 @@ class BatchPlan:
     The plan refers to the matrices' memory: keep ``mats`` alive while it is used.
     """
 
-    def __init__(self, mats, stream=None):
+    def __init__(self, mats, stream=None, tile: int = 0):
+        """``tile`` 64 or 128 forces that round width for every graph; 0 takes
+        each graph's width from the device's batched tuning table."""
         import torch
 
         self.mats = list(mats)
@@ -249,9 +258,9 @@ class BatchPlan:
         ptrs, ns, lds, dt, dev = _batch_arrays(self.mats)
         self.device = dev
         with torch.cuda.device(dev) if dev is not None else _nullcontext():
-            _check(_LIB.apsp_batched_plan_create(ptrs, ns, lds, len(self.mats), dt,
-                                                 _stream(stream), ctypes.byref(self._plan)),
-                   "apsp_batched_plan_create")
+            _check(_LIB.apsp_batched_plan_create_tiled(ptrs, ns, lds, len(self.mats), dt, tile,
+                                                       _stream(stream), ctypes.byref(self._plan)),
+                   "apsp_batched_plan_create_tiled")
 
     def run(self, stream=None):
         import torch
@@ -276,6 +285,32 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def batched_tuning() -> list:
+    """The current device's batched round widths per size bucket (bucket b < 8:
+    n in (64b, 64b + 64]; bucket 8: n > 512)."""
+    out = (ctypes.c_int32 * TUNE_BUCKETS)()
+    _check(_LIB.apsp_batched_tuning_get(out, TUNE_BUCKETS), "apsp_batched_tuning_get")
+    return list(out)
+
+
+def set_batched_tuning(widths) -> None:
+    """Replace the current device's batched round widths (9 entries, 64 or 128)."""
+    widths = list(widths)
+    arr = (ctypes.c_int32 * len(widths))(*widths)
+    _check(_LIB.apsp_batched_tuning_set(arr, len(widths)), "apsp_batched_tuning_set")
+
+
+def batched_autotune(dtype: int = APSP_I32, batch_elems: int = 1 << 24, stream=None) -> dict:
+    """Time both batched round widths per size bucket on the current device and
+    keep the faster; returns {"widths": [...], "ms": [(ms_128, ms_64), ...]}."""
+    table = (ctypes.c_int32 * TUNE_BUCKETS)()
+    ms = (ctypes.c_double * (2 * TUNE_BUCKETS))()
+    _check(_LIB.apsp_batched_autotune(dtype, batch_elems, _stream(stream), table, ms),
+           "apsp_batched_autotune")
+    return {"widths": list(table),
+            "ms": [(float(ms[2 * b]), float(ms[2 * b + 1])) for b in range(TUNE_BUCKETS)]}
 
 
 class _nullcontext:

@@ -17,6 +17,7 @@ struct apsp_batch_plan {
     apsp::BatchDesc *d_descs = nullptr;
     apsp::BatchItem *d_items = nullptr;
     struct Launch {
+        int tile;  // 128 or 64
         int r;
         bool close_only;
         apsp::XcdRanges ranges;
@@ -28,17 +29,14 @@ struct apsp_batch_plan {
 
 namespace apsp {
 
-namespace {
-
-constexpr int kB = kRoundB;
-
-int rounds_of(int n) { return (n + kB - 1) / kB; }
-
-}  // namespace
-
-// Build the plan's host tables; returns APSP_OK or APSP_ERR_INVALID_VALUE.
+// Build the plan's host tables: every graph gets the round width the batched
+// tuning table holds for its size, and each width group gets its own
+// sequence of launches (phase 1 of round 0; then phases 2 and 3 of every
+// round, with the closure of the next diagonal block fused into phase 3).
+// `tile` 64 or 128 forces that width for every graph; 0 takes the table's.
 int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, const int64_t *lds,
-                   int32_t count, std::vector<BatchDesc> &descs, std::vector<BatchItem> &items) {
+                   int32_t count, int tile, std::vector<BatchDesc> &descs,
+                   std::vector<BatchItem> &items) {
     descs.clear();
     items.clear();
     for (int32_t g = 0; g < count; ++g) {
@@ -52,73 +50,84 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
     }
     const int G = (int)descs.size();
     if (G == 0) return APSP_OK;
-    // Balance graphs over the 8 XCDs by tile work (longest first, least
-    // loaded XCD), so each XCD's item list of every launch is about as long.
-    std::vector<int> order(G), xcd(G, 0);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return descs[a].n > descs[b].n; });
-    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int g : order) {
-        const double q = rounds_of(descs[g].n);
-        const int best = (int)(std::min_element(load, load + 8) - load);
-        xcd[g] = best;
-        load[best] += q * q * q;
-    }
-    int qmax = 0;
-    for (const auto &d : descs) qmax = std::max(qmax, rounds_of(d.n));
+    std::vector<int> width(G);
+    for (int g = 0; g < G; ++g) width[g] = tile ? tile : batched_tile(descs[g].n);
+    for (int W : {128, 64}) {
+        auto rounds_of = [W](int n) { return (n + W - 1) / W; };
+        std::vector<int> order;
+        for (int g = 0; g < G; ++g)
+            if (width[g] == W) order.push_back(g);
+        if (order.empty()) continue;
+        // Balance graphs over the 8 XCDs by tile work (longest first, least
+        // loaded XCD), so each XCD's item list of every launch is about as long.
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return descs[a].n > descs[b].n; });
+        std::vector<int> xcd(G, 0);
+        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int g : order) {
+            const double q = rounds_of(descs[g].n);
+            const int best = (int)(std::min_element(load, load + 8) - load);
+            xcd[g] = best;
+            load[best] += q * q * q;
+        }
+        int qmax = 0;
+        for (int g : order) qmax = std::max(qmax, rounds_of(descs[g].n));
 
-    std::vector<BatchItem> per[8];
-    auto flush = [&](int r, bool close_only) {
-        apsp_batch_plan::Launch L;
-        L.r = r;
-        L.close_only = close_only;
-        for (int x = 0; x < 8; ++x) {
-            L.ranges.offset[x] = (int32_t)items.size();
-            L.ranges.count[x] = (int32_t)per[x].size();
-            items.insert(items.end(), per[x].begin(), per[x].end());
-            per[x].clear();
-        }
-        p.launches.push_back(L);
-    };
-    auto push = [&](int g, int I, int J) {
-        BatchItem it;
-        it.graph = g;
-        it.ij = (I << 16) | J;
-        per[xcd[g]].push_back(it);
-    };
-    // launch 0: phase 1 of round 0, every graph
-    for (int g : order) push(g, 0, 0);
-    flush(0, true);
-    for (int r = 0; r < qmax; ++r) {
-        for (int g : order) {  // phase 2 of round r
-            const int q = rounds_of(descs[g].n);
-            if (q <= r || q == 1) continue;
-            for (int J = 0; J < q; ++J)
-                if (J != r) push(g, r, J);
-            for (int I = 0; I < q; ++I)
-                if (I != r) push(g, I, r);
-        }
-        flush(r, false);
-        // phase 3 of round r.  The workgroup of diagonal block r+1 also
-        // closes it, so it runs about twice as long: those items go first,
-        // where they overlap the rest of the launch instead of its tail.
-        for (int g : order) {
-            const int q = rounds_of(descs[g].n);
-            if (q <= r || q == 1) continue;
-            if (r + 1 < q) push(g, r + 1, r + 1);
-        }
-        for (int g : order) {
-            const int q = rounds_of(descs[g].n);
-            if (q <= r || q == 1) continue;
-            for (int I = 0; I < q; ++I)
+        std::vector<BatchItem> per[8];
+        auto flush = [&](int r, bool close_only) {
+            apsp_batch_plan::Launch L;
+            L.tile = W;
+            L.r = r;
+            L.close_only = close_only;
+            for (int x = 0; x < 8; ++x) {
+                L.ranges.offset[x] = (int32_t)items.size();
+                L.ranges.count[x] = (int32_t)per[x].size();
+                items.insert(items.end(), per[x].begin(), per[x].end());
+                per[x].clear();
+            }
+            p.launches.push_back(L);
+        };
+        auto push = [&](int g, int I, int J) {
+            BatchItem it;
+            it.graph = g;
+            it.ij = (I << 16) | J;
+            per[xcd[g]].push_back(it);
+        };
+        for (int g : order) push(g, 0, 0);  // phase 1 of round 0, every graph
+        flush(0, true);
+        for (int r = 0; r < qmax; ++r) {
+            for (int g : order) {  // phase 2 of round r
+                const int q = rounds_of(descs[g].n);
+                if (q <= r || q == 1) continue;
                 for (int J = 0; J < q; ++J)
-                    if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
+                    if (J != r) push(g, r, J);
+                for (int I = 0; I < q; ++I)
+                    if (I != r) push(g, I, r);
+            }
+            flush(r, false);
+            // phase 3 of round r.  The workgroup of diagonal block r+1 also
+            // closes it, so it runs longer: those items go first, where they
+            // overlap the rest of the launch instead of its tail.
+            for (int g : order) {
+                const int q = rounds_of(descs[g].n);
+                if (q <= r || q == 1) continue;
+                if (r + 1 < q) push(g, r + 1, r + 1);
+            }
+            for (int g : order) {
+                const int q = rounds_of(descs[g].n);
+                if (q <= r || q == 1) continue;
+                for (int I = 0; I < q; ++I)
+                    for (int J = 0; J < q; ++J)
+                        if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
+            }
+            flush(r, false);
         }
-        flush(r, false);
     }
     p.items = (int64_t)items.size();
-    p.tiles = p.items - G;
+    p.tiles = 0;
+    for (const auto &L : p.launches)
+        if (!L.close_only)
+            for (int x = 0; x < 8; ++x) p.tiles += L.ranges.count[x];
     return APSP_OK;
 }
 
@@ -158,8 +167,10 @@ void free_plan_buffers(apsp_batch_plan *p, hipStream_t s) {
 // Create a plan; `stream_ordered` selects hipMallocAsync on `s` (one-shot use)
 // instead of hipMalloc.
 int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, int32_t count,
-                    int32_t dtype, hipStream_t s, bool stream_ordered, apsp_batch_plan **out) {
+                    int32_t dtype, int32_t tile, hipStream_t s, bool stream_ordered,
+                    apsp_batch_plan **out) {
     *out = nullptr;
+    if (tile != 0 && tile != 64 && tile != 128) return APSP_ERR_INVALID_VALUE;
     const int32_t st = check_batch(ptrs, ns, lds, count, dtype);
     if (st != APSP_OK) return st;
     apsp_batch_plan *p = new (std::nothrow) apsp_batch_plan();
@@ -169,7 +180,7 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
     p->device = -1;
     std::vector<apsp::BatchDesc> descs;
     std::vector<apsp::BatchItem> items;
-    if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, descs, items);
+    if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, tile, descs, items);
     if (!descs.empty()) {  // an empty batch makes no HIP call at all
         if (hipGetDevice(&p->device) != hipSuccess) {
             delete p;
@@ -210,10 +221,17 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
 }
 
 int32_t plan_run(const apsp_batch_plan *p, hipStream_t s) {
-    for (const auto &L : p->launches)
-        if (apsp::launch_batched_items(p->d_descs, p->d_items, L.ranges, L.r, L.close_only,
-                                       p->dtype, s) != hipSuccess)
+    for (const auto &L : p->launches) {
+        const hipError_t e =
+            L.tile == 64 ? apsp::launch_batched64_items(p->d_descs, p->d_items, L.ranges, L.r,
+                                                        L.close_only, p->dtype, s)
+                         : apsp::launch_batched_items(p->d_descs, p->d_items, L.ranges, L.r,
+                                                      L.close_only, p->dtype, s);
+        if (e != hipSuccess) {
+            apsp::note_error("batched launch", e);
             return APSP_ERR_DEVICE;
+        }
+    }
     return APSP_OK;
 }
 
@@ -225,8 +243,16 @@ int32_t apsp_batched_plan_create(void *const *ptrs, const int32_t *ns, const int
                                  int32_t count, int32_t dtype, void *stream,
                                  apsp_batch_plan **plan) {
     if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
-    return plan_create(ptrs, ns, lds, count, dtype, reinterpret_cast<hipStream_t>(stream), false,
-                       plan);
+    return plan_create(ptrs, ns, lds, count, dtype, 0, reinterpret_cast<hipStream_t>(stream),
+                       false, plan);
+}
+
+int32_t apsp_batched_plan_create_tiled(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                       int32_t count, int32_t dtype, int32_t tile, void *stream,
+                                       apsp_batch_plan **plan) {
+    if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
+    return plan_create(ptrs, ns, lds, count, dtype, tile, reinterpret_cast<hipStream_t>(stream),
+                       false, plan);
 }
 
 int32_t apsp_batched_plan_run(const apsp_batch_plan *plan, void *stream) {
@@ -259,7 +285,7 @@ int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_
                               int32_t count, int32_t dtype, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     apsp_batch_plan *p = nullptr;
-    const int32_t st = plan_create(ptrs, ns, lds, count, dtype, s, true, &p);
+    const int32_t st = plan_create(ptrs, ns, lds, count, dtype, 0, s, true, &p);
     if (st != APSP_OK) return st;
     const int32_t rs = plan_run(p, s);
     free_plan_buffers(p, s);  // stream-ordered: freed after the launches

@@ -62,7 +62,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 }  // namespace
 
-int batched_tile(int64_t) { return TB; }
 
 hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
                                 const XcdRanges &ranges, int r, bool close_only, int dtype,

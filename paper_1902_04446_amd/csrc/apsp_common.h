@@ -96,7 +96,13 @@ hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, 
 hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
                                 const XcdRanges &ranges, int r, bool close_only, int dtype,
                                 hipStream_t s);
+hipError_t launch_batched64_items(const BatchDesc *descs, const BatchItem *items,
+                                  const XcdRanges &ranges, int r, bool close_only, int dtype,
+                                  hipStream_t s);
+// Batched round width (64 or 128) for a graph of n vertices, from the
+// batched tuning table (apsp_autotune.hip).
 int batched_tile(int64_t n);
+constexpr int kTuneBuckets = 9;  // n in (64(b-1), 64b] for b = 1..8, and n > 512
 
 // C = A (x) B, or C = min(C, A (x) B) when accumulate; C is m x n, A m x k,
 // B k x n, row-major with the given leading dimensions; C must not overlap

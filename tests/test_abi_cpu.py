@@ -113,6 +113,35 @@ def test_batched_plan_argument_validation(lib):
     assert lib.apsp_batched_plan_destroy(None) == 0
 
 
+def test_tiled_plan_and_tuning_argument_validation(lib):
+    vp = ctypes.c_void_p
+    plan = vp(None)
+    ns = (ctypes.c_int32 * 2)(4, 5)
+    ptrs = (vp * 2)(0x1000, 0x2000)
+    for bad_tile in (-1, 1, 32, 96, 256):
+        assert lib.apsp_batched_plan_create_tiled(ptrs, ns, None, 2, 0, bad_tile, None,
+                                                  ctypes.byref(plan)) == 1
+    assert lib.apsp_batched_plan_create_tiled(ptrs, ns, None, 2, 0, 64, None, None) == 1
+    assert not plan
+    for tile in (0, 64, 128):  # an empty batch needs no device, whatever the width
+        assert lib.apsp_batched_plan_create_tiled(None, None, None, 0, 1, tile, None,
+                                                  ctypes.byref(plan)) == 0
+        assert plan
+        assert lib.apsp_batched_plan_destroy(plan) == 0
+        plan = vp(None)
+    nb = 9
+    good = (ctypes.c_int32 * nb)(*([128] * nb))
+    bad = (ctypes.c_int32 * nb)(*([64] * 8 + [100]))
+    assert lib.apsp_batched_tuning_set(None, nb) == 1
+    assert lib.apsp_batched_tuning_set(good, nb - 1) == 1
+    assert lib.apsp_batched_tuning_set(bad, nb) == 1
+    assert lib.apsp_batched_tuning_get(None, nb) == 1
+    assert lib.apsp_batched_tuning_get(good, 10) == 1
+    assert lib.apsp_batched_autotune(2, 1 << 24, None, None, None) == 1      # dtype
+    assert lib.apsp_batched_autotune(0, 1 << 19, None, None, None) == 1      # batch too small
+    assert lib.apsp_batched_autotune(0, (1 << 30) + 1, None, None, None) == 1
+
+
 def test_minplus_and_squaring_argument_validation(lib):
     vp = ctypes.c_void_p
     a, b, c = vp(0x10000), vp(0x80000), vp(0x100000)

@@ -358,6 +358,99 @@ def test_batched_plan_reuse(apsp, dev):
     plan.close()
 
 
+@pytest.fixture
+def default_tuning(apsp):
+    """Leave the device's batched tuning table as every other test expects it."""
+    apsp.set_batched_tuning([128] * apsp.TUNE_BUCKETS)
+    yield
+    apsp.set_batched_tuning([128] * apsp.TUNE_BUCKETS)
+
+
+def _directed_int(n, seed):
+    """Directed ER graph with a nonzero diagonal and some 'no edge' entries above 2^30."""
+    rng = gg.rng_for(gg.CFG_TEST, seed)
+    W = rng.integers(1, 1000, size=(n, n)).astype(np.int32)
+    W[rng.random((n, n)) > min(1.0, 6.0 / max(n, 1))] = INF + 5
+    np.fill_diagonal(W, rng.integers(1, 50, size=n).astype(np.int32))
+    return W
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_batched_forced_width_int32_exact(apsp, dev, tile):
+    import torch
+
+    sizes = _batched_case_sizes() + [1000]
+    Ws = [_directed_int(n, 800 + n) for n in sizes]
+    mats = [_to_dev(W, dev, ld=W.shape[0] + (n % 3))[0] for W, n in zip(Ws, sizes)]
+    plan = apsp.BatchPlan(mats, tile=tile)
+    # launches: phase 1 of round 0, then phases 2 and 3 of every round of the largest graph
+    assert plan.info()["launches"] == 1 + 2 * (-(-1000 // tile))
+    plan.run()
+    torch.cuda.synchronize()
+    for W, m in zip(Ws, mats):
+        assert np.array_equal(m.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
+    plan.close()
+
+
+def test_batched_width64_fp32_bitexact(apsp, dev):
+    import torch
+
+    Ws = [_swiss(n, 900 + n)[0] if n > 11 else np.zeros((n, n), np.float32)
+          for n in _batched_case_sizes()]
+    mats = [_to_dev(W, dev, ld=W.shape[0] + 1)[0] for W in Ws]  # unaligned rows
+    plan = apsp.BatchPlan(mats, tile=64)
+    plan.run()
+    torch.cuda.synchronize()
+    for W, m in zip(Ws, mats):
+        got = m.cpu().numpy()
+        assert np.array_equal(got, oracle.blocked(W, 64)), W.shape
+        _assert_f32_close(got, oracle.fw(W))
+    plan.close()
+
+
+def test_batched_mixed_width_table(apsp, dev, default_tuning):
+    """Graphs of one batch split over both widths by the tuning table."""
+    import torch
+
+    table = [64, 128, 64, 128, 64, 128, 64, 128, 64]
+    apsp.set_batched_tuning(table)
+    assert apsp.batched_tuning() == table
+    sizes = [1, 50, 64, 65, 100, 128, 129, 190, 256, 300, 400, 450, 512, 513, 700]
+    for n in sizes:
+        b = 0 if n <= 64 else (min(n, 513) - 1) // 64 if n <= 512 else 8
+        assert apsp.batched_round_width(n, apsp.APSP_F32) == table[b], n
+    Ws = [_swiss(n, 950 + n)[0] if n > 11 else np.zeros((n, n), np.float32) for n in sizes]
+    views = [_to_dev(W, dev)[0] for W in Ws]
+    apsp.solve_batched(views)  # one-shot plan
+    Wi = [_directed_int(n, 960 + n) for n in sizes]
+    vi = [_to_dev(W, dev)[0] for W in Wi]
+    apsp.solve_batched(vi)
+    torch.cuda.synchronize()
+    for W, v, n in zip(Ws, views, sizes):
+        assert np.array_equal(v.cpu().numpy(),
+                              oracle.blocked(W, apsp.batched_round_width(n, apsp.APSP_F32))), n
+    for W, v in zip(Wi, vi):
+        assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
+
+
+def test_batched_autotune(apsp, dev, default_tuning):
+    import torch
+
+    res = apsp.batched_autotune(apsp.APSP_I32, batch_elems=1 << 22)
+    print(f"autotune widths {res['widths']} ms {res['ms']}")
+    assert len(res["widths"]) == apsp.TUNE_BUCKETS
+    assert all(w in (64, 128) for w in res["widths"])
+    assert all(a > 0 and b > 0 for a, b in res["ms"])
+    assert apsp.batched_tuning() == res["widths"]
+    # the tuned table is what plans now use, and results stay exact
+    Ws = gg.batched_graphs(64, item=3)
+    views = [torch.from_numpy(W).to(dev) for W in Ws]
+    apsp.solve_batched(views)
+    torch.cuda.synchronize()
+    for W, v in zip(Ws, views):
+        assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
+
+
 # -------------------------------------------------- min-plus product, squaring
 
 def _rand_operand(shape, dtype, seed, p_inf=0.3):
