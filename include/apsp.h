@@ -137,10 +137,10 @@ int32_t apsp_round_width(int64_t n, int32_t dtype);
  *   ns[g]    n_g, 0 <= n_g <= APSP_BATCHED_MAX_N.
  *   count    number of graphs, >= 0 (0: no-op; ptrs/ns may then be NULL).
  * Every graph goes through the rounds of the blocked method (Sec. 4.4/4.5)
- * with round width b = apsp_batched_round_width(n_g) (64 or 128); each
- * launch covers one phase of one round for all graphs of one width
- * (1 + 2 * max_g ceil(n_g/b) launches per width in use).  int32 results are
- * exactly apsp_solve's.  Builds a one-shot plan: its tables are
+ * with its own round width b_g = apsp_batched_round_width(n_g) (64 or 128);
+ * each launch covers one phase of round r for every graph that has a round
+ * r at its width (1 + 2 * max_g ceil(n_g / b_g) launches).  int32 results
+ * are exactly apsp_solve's.  Builds a one-shot plan: its tables are
  * copied to stream-ordered device memory (hipMallocAsync) and freed
  * stream-ordered after the launches.
  * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY or
@@ -213,6 +213,24 @@ int32_t apsp_batched_plan_create_tiled(void *const *ptrs, const int32_t *ns, con
  * They return APSP_ERR_INVALID_VALUE for bad arguments and APSP_ERR_DEVICE
  * when there is no current device.
  */
+/*
+ * apsp_batched_autotune_batch -- tune the table for a given batch: the
+ * graphs (arguments as apsp_batched_plan_create; count >= 1 and at least
+ * one non-empty graph) are copied twice into library-owned memory
+ * (hipMalloc, 2 x 4 x sum n_g * roundup(n_g, 4) bytes, freed on return), and
+ * the copies are solved under greedy choices: every bucket 128 first, then
+ * each bucket in the batch, in decreasing order of its share of sum n^3, is
+ * switched to 64 and kept there if the whole batch solves at least 3%
+ * faster (each timing is the best of five solves from the pristine copy).
+ * The caller's matrices are only read.  Runs on `stream` and waits for it;
+ * stores the result in the current device's table.  table (nullable)
+ * receives the widths, ms (nullable, 2 doubles) the milliseconds per solve
+ * with every bucket 128 and with the chosen table.
+ */
+int32_t apsp_batched_autotune_batch(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                    int32_t count, int32_t dtype, void *stream, int32_t *table,
+                                    double *ms);
+
 #define APSP_TUNE_BUCKETS 9
 int32_t apsp_batched_tuning_get(int32_t *table, int32_t count);
 int32_t apsp_batched_tuning_set(const int32_t *table, int32_t count);

@@ -19,6 +19,7 @@ __all__ = [
     "minplus", "solve_squaring", "squarings", "solve_symmetric",
     "round_width", "batched_round_width", "num_rounds", "version",
     "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
+    "batched_autotune_batch",
 ]
 
 APSP_I32 = 0
@@ -75,6 +76,8 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_tuning_set": ([ctypes.POINTER(i32), i32], i32),
         "apsp_batched_autotune": ([i32, i64, vp, ctypes.POINTER(i32),
                                    ctypes.POINTER(ctypes.c_double)], i32),
+        "apsp_batched_autotune_batch": ([vp, vp, vp, i32, i32, vp, ctypes.POINTER(i32),
+                                         ctypes.POINTER(ctypes.c_double)], i32),
         "apsp_status_string": ([i32], ctypes.c_char_p),
         "apsp_version": ([], ctypes.c_char_p),
         "apsp_minplus": ([vp, i64, vp, i64, vp, i64, i64, i64, i64, i32, i32, vp], i32),
@@ -311,6 +314,22 @@ def batched_autotune(dtype: int = APSP_I32, batch_elems: int = 1 << 24, stream=N
            "apsp_batched_autotune")
     return {"widths": list(table),
             "ms": [(float(ms[2 * b]), float(ms[2 * b + 1])) for b in range(TUNE_BUCKETS)]}
+
+
+def batched_autotune_batch(mats, stream=None) -> dict:
+    """Tune the current device's batched round widths for this batch (solved
+    on copies; ``mats`` is only read); returns {"widths": [...],
+    "ms_all_128": t0, "ms_tuned": t1}."""
+    import torch
+
+    mats = list(mats)
+    ptrs, ns, lds, dt, dev = _batch_arrays(mats)
+    table = (ctypes.c_int32 * TUNE_BUCKETS)()
+    ms = (ctypes.c_double * 2)()
+    with torch.cuda.device(dev) if dev is not None else _nullcontext():
+        _check(_LIB.apsp_batched_autotune_batch(ptrs, ns, lds, len(mats), dt, _stream(stream),
+                                                table, ms), "apsp_batched_autotune_batch")
+    return {"widths": list(table), "ms_all_128": float(ms[0]), "ms_tuned": float(ms[1])}
 
 
 class _nullcontext:

@@ -14,10 +14,12 @@ struct apsp_batch_plan {
     int dtype = 0;
     int device = 0;
     bool stream_ordered = false;  // buffers from hipMallocAsync (one-shot plans)
-    apsp::BatchDesc *d_descs = nullptr;
+    apsp::BatchDesc *d_descs = nullptr;  // graphs descriptors, then (int32) wmax
     apsp::BatchItem *d_items = nullptr;
+    uint32_t *d_wmax = nullptr;          // int32: largest finite weight per graph
+    int32_t graphs = 0;                  // non-empty graphs
+    apsp::XcdRanges scan = {};           // int32: the 128 x 128 tiles the weight scan reads
     struct Launch {
-        int tile;  // 128 or 64
         int r;
         bool close_only;
         apsp::XcdRanges ranges;
@@ -29,13 +31,15 @@ struct apsp_batch_plan {
 
 namespace apsp {
 
-// Build the plan's host tables: every graph gets the round width the batched
-// tuning table holds for its size, and each width group gets its own
-// sequence of launches (phase 1 of round 0; then phases 2 and 3 of every
-// round, with the closure of the next diagonal block fused into phase 3).
-// `tile` 64 or 128 forces that width for every graph; 0 takes the table's.
+// Build the plan's host tables.  Every graph gets a round width (64 or 128):
+// `tile` forces one for all, else `table` (per size bucket) when given, else
+// the device's tuning table.  Launch 0 is phase 1 of round 0 for every
+// graph; launches 2r+1 and 2r+2 are phases 2 and 3 of round r for every
+// graph that has a round r at its own width, with the closure of diagonal
+// block r+1 fused into phase 3.  int32 plans also list the 128 x 128 tiles
+// of every graph for the weight scan that precedes the solve.
 int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, const int64_t *lds,
-                   int32_t count, int tile, std::vector<BatchDesc> &descs,
+                   int32_t count, int tile, const int32_t *table, std::vector<BatchDesc> &descs,
                    std::vector<BatchItem> &items) {
     descs.clear();
     items.clear();
@@ -45,82 +49,102 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
         d.ptr = static_cast<uint32_t *>(ptrs[g]);
         d.ld = lds ? lds[g] : (ns[g] > 1 ? ns[g] : 1);
         d.n = ns[g];
-        d.pad_ = 0;
+        d.tile = tile ? tile : table ? table[batched_bucket(ns[g])] : batched_tile(ns[g]);
         descs.push_back(d);
     }
     const int G = (int)descs.size();
+    p.graphs = G;
     if (G == 0) return APSP_OK;
-    std::vector<int> width(G);
-    for (int g = 0; g < G; ++g) width[g] = tile ? tile : batched_tile(descs[g].n);
-    for (int W : {128, 64}) {
-        auto rounds_of = [W](int n) { return (n + W - 1) / W; };
-        std::vector<int> order;
-        for (int g = 0; g < G; ++g)
-            if (width[g] == W) order.push_back(g);
-        if (order.empty()) continue;
-        // Balance graphs over the 8 XCDs by tile work (longest first, least
-        // loaded XCD), so each XCD's item list of every launch is about as long.
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return descs[a].n > descs[b].n; });
-        std::vector<int> xcd(G, 0);
-        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int g : order) {
-            const double q = rounds_of(descs[g].n);
-            const int best = (int)(std::min_element(load, load + 8) - load);
-            xcd[g] = best;
-            load[best] += q * q * q;
-        }
-        int qmax = 0;
-        for (int g : order) qmax = std::max(qmax, rounds_of(descs[g].n));
+    auto rounds_of = [&](int g) { return (descs[g].n + descs[g].tile - 1) / descs[g].tile; };
 
-        std::vector<BatchItem> per[8];
-        auto flush = [&](int r, bool close_only) {
-            apsp_batch_plan::Launch L;
-            L.tile = W;
-            L.r = r;
-            L.close_only = close_only;
-            for (int x = 0; x < 8; ++x) {
-                L.ranges.offset[x] = (int32_t)items.size();
-                L.ranges.count[x] = (int32_t)per[x].size();
-                items.insert(items.end(), per[x].begin(), per[x].end());
-                per[x].clear();
-            }
-            p.launches.push_back(L);
-        };
-        auto push = [&](int g, int I, int J) {
-            BatchItem it;
-            it.graph = g;
-            it.ij = (I << 16) | J;
-            per[xcd[g]].push_back(it);
-        };
-        for (int g : order) push(g, 0, 0);  // phase 1 of round 0, every graph
-        flush(0, true);
-        for (int r = 0; r < qmax; ++r) {
+    // Balance graphs over the 8 XCDs by work (longest first, least loaded
+    // XCD), so each XCD's item list of every launch is about as long.
+    std::vector<int> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return descs[a].n > descs[b].n; });
+    std::vector<int> xcd(G, 0);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int qmax = 0;
+    for (int g : order) {
+        const double q = rounds_of(g), w = descs[g].tile;
+        const int best = (int)(std::min_element(load, load + 8) - load);
+        xcd[g] = best;
+        load[best] += q * q * q * w * w * w;
+        qmax = std::max(qmax, rounds_of(g));
+    }
+
+    std::vector<BatchItem> per[8];
+    auto flush = [&](int r, bool close_only) {
+        apsp_batch_plan::Launch L;
+        L.r = r;
+        L.close_only = close_only;
+        for (int x = 0; x < 8; ++x) {
+            L.ranges.offset[x] = (int32_t)items.size();
+            L.ranges.count[x] = (int32_t)per[x].size();
+            items.insert(items.end(), per[x].begin(), per[x].end());
+            per[x].clear();
+        }
+        p.launches.push_back(L);
+    };
+    auto push = [&](int g, int I, int J) {
+        BatchItem it;
+        it.graph = g;
+        it.ij = (I << 16) | J;
+        per[xcd[g]].push_back(it);
+    };
+    // Within a launch the longest items go first, where they overlap the
+    // rest of the launch instead of its tail: 128-wide before 64-wide, and in
+    // phase 3 the diagonal block r+1 (whose workgroup also closes it) first.
+    const int widths[2] = {128, 64};
+    for (int W : widths)
+        for (int g : order)
+            if (descs[g].tile == W) push(g, 0, 0);  // phase 1 of round 0, every graph
+    flush(0, true);
+    for (int r = 0; r < qmax; ++r) {
+        for (int W : widths)
             for (int g : order) {  // phase 2 of round r
-                const int q = rounds_of(descs[g].n);
-                if (q <= r || q == 1) continue;
+                const int q = rounds_of(g);
+                if (descs[g].tile != W || q <= r || q == 1) continue;
                 for (int J = 0; J < q; ++J)
                     if (J != r) push(g, r, J);
                 for (int I = 0; I < q; ++I)
                     if (I != r) push(g, I, r);
             }
-            flush(r, false);
-            // phase 3 of round r.  The workgroup of diagonal block r+1 also
-            // closes it, so it runs longer: those items go first, where they
-            // overlap the rest of the launch instead of its tail.
+        flush(r, false);
+        for (int W : widths) {  // phase 3 of round r
             for (int g : order) {
-                const int q = rounds_of(descs[g].n);
-                if (q <= r || q == 1) continue;
+                const int q = rounds_of(g);
+                if (descs[g].tile != W || q <= r || q == 1) continue;
                 if (r + 1 < q) push(g, r + 1, r + 1);
             }
             for (int g : order) {
-                const int q = rounds_of(descs[g].n);
-                if (q <= r || q == 1) continue;
+                const int q = rounds_of(g);
+                if (descs[g].tile != W || q <= r || q == 1) continue;
                 for (int I = 0; I < q; ++I)
                     for (int J = 0; J < q; ++J)
                         if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
             }
-            flush(r, false);
+        }
+        flush(r, false);
+    }
+    if (p.dtype == APSP_I32) {
+        std::vector<BatchItem> scan[8];
+        int64_t next = 0;
+        for (int g = 0; g < G; ++g) {
+            const int q = (descs[g].n + kRoundB - 1) / kRoundB;
+            for (int I = 0; I < q; ++I)
+                for (int J = 0; J < q; ++J) {
+                    BatchItem it;
+                    it.graph = g;
+                    it.ij = (I << 16) | J;
+                    scan[next++ & 7].push_back(it);
+                }
+        }
+        for (int x = 0; x < 8; ++x) {
+            p.scan.offset[x] = (int32_t)items.size();
+            p.scan.count[x] = (int32_t)scan[x].size();
+            items.insert(items.end(), scan[x].begin(), scan[x].end());
         }
     }
     p.items = (int64_t)items.size();
@@ -162,15 +186,19 @@ void free_plan_buffers(apsp_batch_plan *p, hipStream_t s) {
     }
     p->d_descs = nullptr;
     p->d_items = nullptr;
+    p->d_wmax = nullptr;
 }
 
 // Create a plan; `stream_ordered` selects hipMallocAsync on `s` (one-shot use)
 // instead of hipMalloc.
 int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, int32_t count,
-                    int32_t dtype, int32_t tile, hipStream_t s, bool stream_ordered,
-                    apsp_batch_plan **out) {
+                    int32_t dtype, int32_t tile, const int32_t *table, hipStream_t s,
+                    bool stream_ordered, apsp_batch_plan **out) {
     *out = nullptr;
     if (tile != 0 && tile != 64 && tile != 128) return APSP_ERR_INVALID_VALUE;
+    if (table)
+        for (int b = 0; b < apsp::kTuneBuckets; ++b)
+            if (table[b] != 64 && table[b] != 128) return APSP_ERR_INVALID_VALUE;
     const int32_t st = check_batch(ptrs, ns, lds, count, dtype);
     if (st != APSP_OK) return st;
     apsp_batch_plan *p = new (std::nothrow) apsp_batch_plan();
@@ -180,13 +208,14 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
     p->device = -1;
     std::vector<apsp::BatchDesc> descs;
     std::vector<apsp::BatchItem> items;
-    if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, tile, descs, items);
+    if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, tile, table, descs, items);
     if (!descs.empty()) {  // an empty batch makes no HIP call at all
         if (hipGetDevice(&p->device) != hipSuccess) {
             delete p;
             return APSP_ERR_DEVICE;
         }
-        const size_t db = descs.size() * sizeof(apsp::BatchDesc);
+        const size_t db = descs.size() * sizeof(apsp::BatchDesc) +
+                          (dtype == APSP_I32 ? descs.size() * sizeof(uint32_t) : 0);
         const size_t ib = items.size() * sizeof(apsp::BatchItem);
         hipError_t e1, e2;
         if (stream_ordered) {
@@ -202,9 +231,11 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
             delete p;
             return APSP_ERR_NO_MEMORY;
         }
+        if (dtype == APSP_I32) p->d_wmax = reinterpret_cast<uint32_t *>(p->d_descs + descs.size());
+        const size_t dcopy = descs.size() * sizeof(apsp::BatchDesc);
         // Pageable sources: both copies have consumed the host vectors when
         // they return.
-        if (hipMemcpyAsync(p->d_descs, descs.data(), db, hipMemcpyHostToDevice, s) != hipSuccess ||
+        if (hipMemcpyAsync(p->d_descs, descs.data(), dcopy, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(p->d_items, items.data(), ib, hipMemcpyHostToDevice, s) != hipSuccess) {
             free_plan_buffers(p, s);
             delete p;
@@ -221,12 +252,17 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
 }
 
 int32_t plan_run(const apsp_batch_plan *p, hipStream_t s) {
+    if (p->d_wmax) {
+        const hipError_t e = apsp::launch_batched_wmax(p->d_descs, p->d_items, p->scan, p->d_wmax,
+                                                       p->graphs, s);
+        if (e != hipSuccess) {
+            apsp::note_error("batched weight scan", e);
+            return APSP_ERR_DEVICE;
+        }
+    }
     for (const auto &L : p->launches) {
-        const hipError_t e =
-            L.tile == 64 ? apsp::launch_batched64_items(p->d_descs, p->d_items, L.ranges, L.r,
-                                                        L.close_only, p->dtype, s)
-                         : apsp::launch_batched_items(p->d_descs, p->d_items, L.ranges, L.r,
-                                                      L.close_only, p->dtype, s);
+        const hipError_t e = apsp::launch_batched_items(p->d_descs, p->d_items, L.ranges, L.r,
+                                                        L.close_only, p->dtype, p->d_wmax, s);
         if (e != hipSuccess) {
             apsp::note_error("batched launch", e);
             return APSP_ERR_DEVICE;
@@ -237,22 +273,29 @@ int32_t plan_run(const apsp_batch_plan *p, hipStream_t s) {
 
 }  // namespace
 
+int32_t apsp::batched_plan_create_table(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                        int32_t count, int32_t dtype, const int32_t *table,
+                                        hipStream_t s, apsp_batch_plan **out) {
+    if (out == nullptr || table == nullptr) return APSP_ERR_INVALID_VALUE;
+    return plan_create(ptrs, ns, lds, count, dtype, 0, table, s, false, out);
+}
+
 extern "C" {
 
 int32_t apsp_batched_plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds,
                                  int32_t count, int32_t dtype, void *stream,
                                  apsp_batch_plan **plan) {
     if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
-    return plan_create(ptrs, ns, lds, count, dtype, 0, reinterpret_cast<hipStream_t>(stream),
-                       false, plan);
+    return plan_create(ptrs, ns, lds, count, dtype, 0, nullptr,
+                       reinterpret_cast<hipStream_t>(stream), false, plan);
 }
 
 int32_t apsp_batched_plan_create_tiled(void *const *ptrs, const int32_t *ns, const int64_t *lds,
                                        int32_t count, int32_t dtype, int32_t tile, void *stream,
                                        apsp_batch_plan **plan) {
     if (plan == nullptr) return APSP_ERR_INVALID_VALUE;
-    return plan_create(ptrs, ns, lds, count, dtype, tile, reinterpret_cast<hipStream_t>(stream),
-                       false, plan);
+    return plan_create(ptrs, ns, lds, count, dtype, tile, nullptr,
+                       reinterpret_cast<hipStream_t>(stream), false, plan);
 }
 
 int32_t apsp_batched_plan_run(const apsp_batch_plan *plan, void *stream) {
@@ -285,7 +328,7 @@ int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_
                               int32_t count, int32_t dtype, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     apsp_batch_plan *p = nullptr;
-    const int32_t st = plan_create(ptrs, ns, lds, count, dtype, 0, s, true, &p);
+    const int32_t st = plan_create(ptrs, ns, lds, count, dtype, 0, nullptr, s, true, &p);
     if (st != APSP_OK) return st;
     const int32_t rs = plan_run(p, s);
     free_plan_buffers(p, s);  // stream-ordered: freed after the launches

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct apsp_batch_plan;  // opaque plan of the C ABI (apsp_batch_plan.hip)
+
 namespace apsp {
 
 constexpr uint32_t kInfI32 = 1u << 30;
@@ -27,6 +29,7 @@ constexpr uint32_t kInfF32Bits = 0x7f800000u;
 
 struct OpI32 {
     static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+    static __device__ __forceinline__ uint32_t out(uint32_t v) { return v; }
     static __device__ __forceinline__ uint32_t min2(uint32_t a, uint32_t b) { return a < b ? a : b; }
     static __device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
         return min2(min2(a, b), c);
@@ -48,18 +51,53 @@ struct OpF32 {
     }
     static __device__ __forceinline__ uint32_t pad() { return kInfF32Bits; }
     static __device__ __forceinline__ uint32_t norm(uint32_t v) { return v; }
+    static __device__ __forceinline__ uint32_t out(uint32_t v) { return v; }
 };
+
+//  * OpI32F: int32 storage, fp32 arithmetic.  Values are converted as they
+//    are loaded (v >= 2^30 -> +inf, else (float)v) and back as they are
+//    stored (+inf -> 2^30).  Exact whenever every sum the method forms is an
+//    integer below 2^24.  Every value the blocked method stores is the length
+//    of a shortest path over some subset of intermediate vertices, so at most
+//    (n-1) * wmax for the largest finite weight wmax, and every sum it forms
+//    adds two of them: 2 (n-1) wmax < 2^24 is sufficient (batched_exact_f32).
+//    fp32 adds issue at a higher rate than uint32 adds on this VALU.
+struct OpI32F {
+    static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) {
+        return __float_as_uint(__uint_as_float(a) + __uint_as_float(b));
+    }
+    static __device__ __forceinline__ uint32_t min2(uint32_t a, uint32_t b) {
+        return (int32_t)a < (int32_t)b ? a : b;
+    }
+    static __device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
+        return min2(min2(a, b), c);
+    }
+    static __device__ __forceinline__ uint32_t pad() { return kInfF32Bits; }
+    static __device__ __forceinline__ uint32_t norm(uint32_t v) {
+        return v >= kInfI32 ? kInfF32Bits : __float_as_uint((float)v);
+    }
+    static __device__ __forceinline__ uint32_t out(uint32_t v) {
+        return v == kInfF32Bits ? kInfI32 : (uint32_t)__uint_as_float(v);
+    }
+};
+
+// Whether a graph of n vertices whose largest finite off-diagonal weight is
+// wmax may take the OpI32F path bit-exactly: 2 (n-1) wmax < 2^24.
+__host__ __device__ __forceinline__ bool batched_exact_f32(int64_t n, uint32_t wmax) {
+    return n <= 1 || (uint64_t)2 * (uint64_t)(n - 1) * wmax < (1u << 24);
+}
 
 // Round width of the single-graph solver and the output tile of the
 // phase-2/phase-3 kernels (one workgroup per 128 x 128 tile).
 constexpr int kRoundB = 128;
 
-// Per-graph descriptor of a batched solve.
+// Per-graph descriptor of a batched solve (tile: the graph's round width, 64
+// or 128).
 struct BatchDesc {
     uint32_t *ptr;
     int64_t ld;
     int32_t n;
-    int32_t pad_;
+    int32_t tile;
 };
 
 // One workgroup's work in a batched launch: tile (I, J) = (ij >> 16, ij & 0xffff)
@@ -93,16 +131,26 @@ int64_t num_rounds(int64_t n);
 int64_t tile_count(int64_t n, int64_t r, int set);
 hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,
                            hipStream_t s);
+// Batched launches (apsp_batched.hip).  `wmax` (int32
+// batches) holds each graph's largest finite weight, from launch_batched_wmax,
+// which zeroes it and scans the 128 x 128 tiles given by its items.
+hipError_t launch_batched_wmax(const BatchDesc *descs, const BatchItem *items,
+                               const XcdRanges &ranges, uint32_t *wmax, int32_t graphs,
+                               hipStream_t s);
 hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
                                 const XcdRanges &ranges, int r, bool close_only, int dtype,
-                                hipStream_t s);
-hipError_t launch_batched64_items(const BatchDesc *descs, const BatchItem *items,
-                                  const XcdRanges &ranges, int r, bool close_only, int dtype,
-                                  hipStream_t s);
+                                const uint32_t *wmax, hipStream_t s);
 // Batched round width (64 or 128) for a graph of n vertices, from the
 // batched tuning table (apsp_autotune.hip).
 int batched_tile(int64_t n);
-constexpr int kTuneBuckets = 9;  // n in (64(b-1), 64b] for b = 1..8, and n > 512
+constexpr int kTuneBuckets = 9;  // bucket b < 8: n in (64b, 64b + 64]; bucket 8: n > 512
+int batched_bucket(int64_t n);
+// Plan with the round width of each graph taken from `table` (kTuneBuckets
+// entries, 64 or 128), for the batched autotuner; arguments as
+// apsp_batched_plan_create.
+int32_t batched_plan_create_table(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                  int32_t count, int32_t dtype, const int32_t *table,
+                                  hipStream_t s, ::apsp_batch_plan **out);
 
 // C = A (x) B, or C = min(C, A (x) B) when accumulate; C is m x n, A m x k,
 // B k x n, row-major with the given leading dimensions; C must not overlap

@@ -33,8 +33,9 @@ __device__ __forceinline__ int row_of(int m, int ty) { return (m >> 2) * 64 + ty
 __device__ __forceinline__ int col_of(int e, int tx) { return (e >> 2) * 64 + tx * 4 + (e & 3); }
 
 // Load the mr x nc tile at (i0, j0) into acc; entries outside are padded with
-// "no edge".  NORM applies the input normalisation on the way in (int32
-// values above 2^30 -> 2^30; a tile on the diagonal gets a zero diagonal).
+// "no edge".  NORM applies the input normalisation on the way in (Op::norm:
+// int32 values above 2^30 -> 2^30, or the conversion of OpI32F; a tile on the
+// diagonal gets a zero diagonal).  store_acc converts back with Op::out.
 template <class Op, bool NORM>
 __device__ __forceinline__ void load_acc(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
                                          int64_t i0, int64_t j0, int mr, int nc, bool vec) {
@@ -90,12 +91,12 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t 
         for (int h = 0; h < 2; ++h) {
             const int col = h * 64 + tx * 4;
             if (vec && col + 3 < nc) {
-                st4(crow + col, make_uint4(acc[m][h * 4 + 0], acc[m][h * 4 + 1],
-                                           acc[m][h * 4 + 2], acc[m][h * 4 + 3]));
+                st4(crow + col, make_uint4(Op::out(acc[m][h * 4 + 0]), Op::out(acc[m][h * 4 + 1]),
+                                           Op::out(acc[m][h * 4 + 2]), Op::out(acc[m][h * 4 + 3])));
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (col + e < nc) crow[col + e] = acc[m][h * 4 + e];
+                    if (col + e < nc) crow[col + e] = Op::out(acc[m][h * 4 + e]);
             }
         }
     }
@@ -118,7 +119,11 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t 
 //   TA: A[i][k] = A[k * lda + i0 + i]      TB: B[k][j] = B[(j0 + j) * ldb + k]
 // The transposed loaders read rows of the stored matrix (coalesced) and
 // scatter them into the same LDS layout.
-template <class Op, bool NORM, bool TA = false, bool TB = false>
+// PARTIAL: a tile whose valid rows (mr <= 64) or columns (nc <= 64) fit in
+// the first half updates only those (acc rows m < 4 / columns e < 4, by
+// quadrant, on workgroup-uniform branches); the other accumulators keep
+// their values.
+template <class Op, bool NORM, bool TA = false, bool TB = false, bool PARTIAL = false>
 __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uint32_t *A, int64_t lda,
                                                 const uint32_t *B, int64_t ldb, int64_t i0,
                                                 int64_t j0, int mr, int nc, int kw, bool vec,
@@ -236,23 +241,72 @@ __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uin
 #pragma unroll 2
         for (int p = 0; p < KC / 2; ++p) {
             uint32_t a0[8], a1[8], b0[8], b1[8];
+            if (!PARTIAL) {
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const uint2 av = L.As[s][p][row_of(m, ty)];
-                a0[m] = av.x;
-                a1[m] = av.y;
+                for (int m = 0; m < 8; ++m) {
+                    const uint2 av = L.As[s][p][row_of(m, ty)];
+                    a0[m] = av.x;
+                    a1[m] = av.y;
+                }
+                const uint4 b00 = L.Bs[s][2 * p][tx], b01 = L.Bs[s][2 * p][16 + tx];
+                const uint4 b10 = L.Bs[s][2 * p + 1][tx], b11 = L.Bs[s][2 * p + 1][16 + tx];
+                b0[0] = b00.x; b0[1] = b00.y; b0[2] = b00.z; b0[3] = b00.w;
+                b0[4] = b01.x; b0[5] = b01.y; b0[6] = b01.z; b0[7] = b01.w;
+                b1[0] = b10.x; b1[1] = b10.y; b1[2] = b10.z; b1[3] = b10.w;
+                b1[4] = b11.x; b1[5] = b11.y; b1[6] = b11.z; b1[7] = b11.w;
+#pragma unroll
+                for (int m = 0; m < 8; ++m)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+            } else {
+                const bool rows2 = mr > 64, cols2 = nc > 64;  // uniform
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const uint2 av = L.As[s][p][row_of(m, ty)];
+                    a0[m] = av.x;
+                    a1[m] = av.y;
+                }
+                const uint4 b00 = L.Bs[s][2 * p][tx], b10 = L.Bs[s][2 * p + 1][tx];
+                b0[0] = b00.x; b0[1] = b00.y; b0[2] = b00.z; b0[3] = b00.w;
+                b1[0] = b10.x; b1[1] = b10.y; b1[2] = b10.z; b1[3] = b10.w;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+                if (cols2) {
+                    const uint4 b01 = L.Bs[s][2 * p][16 + tx], b11 = L.Bs[s][2 * p + 1][16 + tx];
+                    b0[4] = b01.x; b0[5] = b01.y; b0[6] = b01.z; b0[7] = b01.w;
+                    b1[4] = b11.x; b1[5] = b11.y; b1[6] = b11.z; b1[7] = b11.w;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int e = 4; e < 8; ++e)
+                            acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+                }
+                if (rows2) {
+#pragma unroll
+                    for (int m = 4; m < 8; ++m) {
+                        const uint2 av = L.As[s][p][row_of(m, ty)];
+                        a0[m] = av.x;
+                        a1[m] = av.y;
+                    }
+#pragma unroll
+                    for (int m = 4; m < 8; ++m)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+                    if (cols2) {
+#pragma unroll
+                        for (int m = 4; m < 8; ++m)
+#pragma unroll
+                            for (int e = 4; e < 8; ++e)
+                                acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]),
+                                                     Op::add(a1[m], b1[e]));
+                    }
+                }
             }
-            const uint4 b00 = L.Bs[s][2 * p][tx], b01 = L.Bs[s][2 * p][16 + tx];
-            const uint4 b10 = L.Bs[s][2 * p + 1][tx], b11 = L.Bs[s][2 * p + 1][16 + tx];
-            b0[0] = b00.x; b0[1] = b00.y; b0[2] = b00.z; b0[3] = b00.w;
-            b0[4] = b01.x; b0[5] = b01.y; b0[6] = b01.z; b0[7] = b01.w;
-            b1[0] = b10.x; b1[1] = b10.y; b1[2] = b10.z; b1[3] = b10.w;
-            b1[4] = b11.x; b1[5] = b11.y; b1[6] = b11.z; b1[7] = b11.w;
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
         }
         if (c + 1 < nch) sstore(s ^ 1);
         __syncthreads();
@@ -260,68 +314,124 @@ __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uin
 }
 
 // The blocked method's form: A = D[i0.., kb .. kb+kw), B = D[kb .. kb+kw, j0..].
-template <class Op, bool NORM>
+template <class Op, bool NORM, bool PARTIAL = false>
 __device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
                                              int64_t i0, int64_t j0, int64_t kb, int mr, int nc,
                                              int kw, bool vec, Lds &L) {
-    minplus_tile_ab<Op, NORM>(acc, D + kb, ld, D + kb * ld, ld, i0, j0, mr, nc, kw, vec, L);
+    minplus_tile_ab<Op, NORM, false, false, PARTIAL>(acc, D + kb, ld, D + kb * ld, ld, i0, j0, mr,
+                                                     nc, kw, vec, L);
 }
 
 // ---------------------------------------------------------------------------
 // Floyd-Warshall closure of a (kw x kw, kw <= 128) diagonal block held in
-// registers in the layout of k_tiles (thread (tx, ty) holds rows
-// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).  Pivot k:
-// the 16 threads holding row k and the 16 holding column k publish them to
-// LDS (double-buffered, one barrier per pivot), then every thread applies
-// d_ij = min(d_ij, d_ik + d_kj) to its 64 entries.  Same operations in the
-// same order as the textbook loop, so the same bits.  `lds` needs 4 x 128 words
-// and every thread returns after the last pivot's barrier.
+// registers in the layout above (thread (tx, ty) holds rows
+// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).
+//
+// Pivots go in ascending pairs (k, k+1), one barrier per pair: the owners of
+// rows k, k+1 and columns k, k+1 publish them to LDS (double-buffered) as
+// they stand before pivot k.  Every thread then forms what pivot k does to
+// row and column k+1 on its own columns / rows,
+//     r1'[j] = min(r1[j], d[k+1][k] + r0[j]),  c1'[i] = min(c1[i], c0[i] + d[k][k+1]),
+// and applies both pivots with one min3:
+//     d[i][j] = min3(d[i][j], c0[i] + r0[j], c1'[i] + r1'[j]).
+// These are the textbook loop's sums (pivot row and column k do not change
+// under pivot k, as d[k][k] = 0) and the minimum is exact, so the bits are
+// those of the sequential loop.  A block of kw <= 64 vertices updates only
+// the quadrant that holds it.  `lds` needs 8 x 128 words; every thread
+// returns after the last pair's barrier.
 // ---------------------------------------------------------------------------
 template <class Op>
 __device__ __forceinline__ void close_block(uint32_t (&acc)[8][8], int kw, uint32_t *lds) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    uint32_t *rowbuf = lds;            // [2][128]
-    uint32_t *colbuf = lds + 2 * TB;   // [2][128]
-    // pivots in ascending order: k = kh*64 + kq*4 + u
+    // a block of at most 64 vertices lives in acc rows m < 4, columns e < 4
+    const bool big = kw > 64;
+    // rowbuf(sel, v) = lds + sel*256 + v*128, colbuf(sel, v) = lds + 512 + sel*256 + v*128
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
         for (int kq = 0; kq < 16; ++kq) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = kh * 64 + kq * 4 + u;
-                if (k < kw) {
-                    const int sel = (k & 1) * TB;
-                    const int mk = kh * 4 + u;  // register row/column index of pivot k
+            for (int up = 0; up < 2; ++up) {
+                const int k = kh * 64 + kq * 4 + up * 2;  // first pivot of the pair
+                if (k < kw) {                             // kw is uniform
+                    const int sel = (k >> 1) & 1;
+                    const int mk = kh * 4 + up * 2;  // register row/column index of pivot k
+                    uint32_t *rb = lds + sel * 256;
+                    uint32_t *cb = lds + 512 + sel * 256;
                     if (ty == kq) {
 #pragma unroll
-                        for (int h = 0; h < 2; ++h)
-                            *reinterpret_cast<uint4 *>(&rowbuf[sel + h * 64 + tx * 4]) =
-                                make_uint4(acc[mk][h * 4 + 0], acc[mk][h * 4 + 1],
-                                           acc[mk][h * 4 + 2], acc[mk][h * 4 + 3]);
+                        for (int v = 0; v < 2; ++v)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+                                *reinterpret_cast<uint4 *>(&rb[v * 128 + h * 64 + tx * 4]) =
+                                    make_uint4(acc[mk + v][h * 4 + 0], acc[mk + v][h * 4 + 1],
+                                               acc[mk + v][h * 4 + 2], acc[mk + v][h * 4 + 3]);
                     }
                     if (tx == kq) {
 #pragma unroll
-                        for (int h = 0; h < 2; ++h)
-                            *reinterpret_cast<uint4 *>(&colbuf[sel + h * 64 + ty * 4]) =
-                                make_uint4(acc[h * 4 + 0][mk], acc[h * 4 + 1][mk],
-                                           acc[h * 4 + 2][mk], acc[h * 4 + 3][mk]);
+                        for (int v = 0; v < 2; ++v)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+                                *reinterpret_cast<uint4 *>(&cb[v * 128 + h * 64 + ty * 4]) =
+                                    make_uint4(acc[h * 4 + 0][mk + v], acc[h * 4 + 1][mk + v],
+                                               acc[h * 4 + 2][mk + v], acc[h * 4 + 3][mk + v]);
                     }
                     __syncthreads();
-                    uint32_t dik[8], dkj[8];
+                    uint32_t c0[8], c1[8];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const uint4 c4 = *reinterpret_cast<const uint4 *>(&colbuf[sel + h * 64 + ty * 4]);
-                        const uint4 r4 = *reinterpret_cast<const uint4 *>(&rowbuf[sel + h * 64 + tx * 4]);
-                        dik[h * 4 + 0] = c4.x; dik[h * 4 + 1] = c4.y;
-                        dik[h * 4 + 2] = c4.z; dik[h * 4 + 3] = c4.w;
-                        dkj[h * 4 + 0] = r4.x; dkj[h * 4 + 1] = r4.y;
-                        dkj[h * 4 + 2] = r4.z; dkj[h * 4 + 3] = r4.w;
+                        const uint4 c = *reinterpret_cast<const uint4 *>(&cb[h * 64 + ty * 4]);
+                        const uint4 d = *reinterpret_cast<const uint4 *>(&cb[128 + h * 64 + ty * 4]);
+                        c0[h * 4 + 0] = c.x; c0[h * 4 + 1] = c.y; c0[h * 4 + 2] = c.z; c0[h * 4 + 3] = c.w;
+                        c1[h * 4 + 0] = d.x; c1[h * 4 + 1] = d.y; c1[h * 4 + 2] = d.z; c1[h * 4 + 3] = d.w;
                     }
+                    if (k + 1 < kw) {
+                        const uint32_t x01 = rb[k + 1];    // d[k][k+1]
+                        const uint32_t x10 = rb[128 + k];  // d[k+1][k]
 #pragma unroll
-                    for (int m = 0; m < 8; ++m)
+                        for (int m = 0; m < 8; ++m) c1[m] = Op::min2(c1[m], Op::add(c0[m], x01));
+                        // one half of the columns at a time keeps fewer values live
 #pragma unroll
-                        for (int e = 0; e < 8; ++e)
-                            acc[m][e] = Op::min2(acc[m][e], Op::add(dik[m], dkj[e]));
+                        for (int h = 0; h < 2; ++h) {
+                            if (h == 1 && !big) break;
+                            const uint4 a = *reinterpret_cast<const uint4 *>(&rb[h * 64 + tx * 4]);
+                            const uint4 b = *reinterpret_cast<const uint4 *>(&rb[128 + h * 64 + tx * 4]);
+                            const uint32_t r0[4] = {a.x, a.y, a.z, a.w};
+                            uint32_t r1[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) r1[e] = Op::min2(r1[e], Op::add(x10, r0[e]));
+#pragma unroll
+                            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    acc[m][h * 4 + e] = Op::min3(acc[m][h * 4 + e], Op::add(c0[m], r0[e]),
+                                                                 Op::add(c1[m], r1[e]));
+                            if (big) {
+#pragma unroll
+                                for (int m = 4; m < 8; ++m)
+#pragma unroll
+                                    for (int e = 0; e < 4; ++e)
+                                        acc[m][h * 4 + e] =
+                                            Op::min3(acc[m][h * 4 + e], Op::add(c0[m], r0[e]),
+                                                     Op::add(c1[m], r1[e]));
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    } else {  // odd kw: the last pivot alone
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (h == 1 && !big) break;
+                            const uint4 a = *reinterpret_cast<const uint4 *>(&rb[h * 64 + tx * 4]);
+                            const uint32_t r0[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                            for (int m = 0; m < 8; ++m) {
+                                if (m >= 4 && !big) break;
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    acc[m][h * 4 + e] =
+                                        Op::min2(acc[m][h * 4 + e], Op::add(c0[m], r0[e]));
+                            }
+                        }
+                    }
                 }
             }
         }

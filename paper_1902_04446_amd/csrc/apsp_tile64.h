@@ -1,27 +1,24 @@
-// 64 x 64-tile form of the round-synchronous batched solver (the schedule is
-// the one of apsp_batched.hip: phase 1 of round 0, then per round r a phase-2
-// launch and a phase-3 launch whose diagonal block r+1 is also closed).
-// Round width 64 wastes less work on padding for graphs just above a multiple
-// of 128 (n = 130 needs two 128-wide rounds, mostly empty, or three 64-wide
-// ones); its tile update keeps a 4 x 4 block per thread, so it does more LDS
-// traffic per update than the 128-wide form.  Which form a graph gets is
-// decided per size bucket by the batched tuning table (apsp_autotune.hip).
-//
-// One workgroup of 256 threads per 64 x 64 tile; thread (tx, ty) =
-// (t % 16, t / 16) keeps rows 4ty .. 4ty+3, columns 4tx .. 4tx+3 in
-// registers for the whole item:
+// Device building blocks of the 64 x 64-tile form of the batched solver:
+// one workgroup of 256 threads per 64 x 64 tile, thread (tx, ty) =
+// (t % 16, t / 16) keeping rows 4ty .. 4ty+3, columns 4tx .. 4tx+3 in
+// registers for the whole item.
 //   update    the 64-wide k range of A (stored as k-pairs) and B is staged in
-//             LDS in full, then c = min3(c, a0 + b0, a1 + b1) per k-pair;
+//             LDS in full, then c = min3(c, a0 + b0, a1 + b1) per k-pair
+//             (arXiv:1902.04446, Table 1: MinPlus);
 //   closure   plain Floyd-Warshall over the register tile, pivots ascending:
 //             the owners of pivot row and column k put them in LDS (double
-//             buffered), one barrier per pivot.
-// Tiles are normalised as they are loaded (int32 clamp at 2^30, zero
-// diagonal on diagonal tiles), as in the 128-wide form.
+//             buffered), one barrier per pivot (Table 1: FloydWarshall).
+// Round width 64 wastes less work on padding than 128 for graphs just above
+// a multiple of 128 and runs a quarter of the closure work per vertex; its
+// 4 x 4 register block does more LDS traffic per update than the 128-wide
+// tile.  Tiles are normalised as they are loaded (Op::norm, zero diagonal on
+// diagonal tiles) and converted back as they are stored (Op::out).
+#pragma once
+
 #include "apsp_common.h"
 
 namespace apsp {
-
-namespace {
+namespace tile64 {
 
 constexpr int T64 = 64;
 constexpr int NT64 = 256;
@@ -78,11 +75,12 @@ __device__ __forceinline__ void store64(const uint32_t (&acc)[4][4], uint32_t *D
         if (row >= mr) continue;
         uint32_t *crow = D + (int64_t)(i0 + row) * ld + j0 + tx * 4;
         if (vec && tx * 4 + 4 <= nc) {
-            *reinterpret_cast<uint4 *>(crow) = make_uint4(acc[m][0], acc[m][1], acc[m][2], acc[m][3]);
+            *reinterpret_cast<uint4 *>(crow) = make_uint4(Op::out(acc[m][0]), Op::out(acc[m][1]),
+                                                          Op::out(acc[m][2]), Op::out(acc[m][3]));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (tx * 4 + e < nc) crow[e] = acc[m][e];
+                if (tx * 4 + e < nc) crow[e] = Op::out(acc[m][e]);
         }
     }
 }
@@ -91,7 +89,7 @@ __device__ __forceinline__ void store64(const uint32_t (&acc)[4][4], uint32_t *D
 // (mr x kw and kw x nc valid).  Both operands are staged in full before the
 // caller stores acc, so the output tile may be one of them (phase 2).
 template <class Op>
-__device__ void update64(uint32_t (&acc)[4][4], const uint32_t *D, int64_t ld, int i0, int j0,
+__device__ __forceinline__ void update64(uint32_t (&acc)[4][4], const uint32_t *D, int64_t ld, int i0, int j0,
                          int kb, int mr, int nc, int kw, bool vec, Lds64 &L) {
     const int t = threadIdx.x;
     const uint32_t PAD = Op::pad();
@@ -166,7 +164,7 @@ __device__ void update64(uint32_t (&acc)[4][4], const uint32_t *D, int64_t ld, i
 // 64), ascending.  Pivot row and column do not change under their own pivot
 // (zero diagonal), so publishing them before the update is exact.
 template <class Op>
-__device__ void close64(uint32_t (&acc)[4][4], int kw, Lds64 &L) {
+__device__ __forceinline__ void close64(uint32_t (&acc)[4][4], int kw, Lds64 &L) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int kq = 0; kq < kw; kq += 4) {
 #pragma unroll
@@ -198,57 +196,5 @@ __device__ void close64(uint32_t (&acc)[4][4], int kw, Lds64 &L) {
     }
 }
 
-template <class Op, bool CLOSE_ONLY>
-__global__ __launch_bounds__(NT64) void k_batched64(const BatchDesc *__restrict__ descs,
-                                                    const BatchItem *__restrict__ items,
-                                                    XcdRanges ranges, int r) {
-    __shared__ Lds64 L;
-    const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    if (slot >= ranges.count[x]) return;  // this XCD's list is shorter
-    const BatchItem it = items[ranges.offset[x] + slot];
-    const BatchDesc g = descs[it.graph];
-    uint32_t *D = g.ptr;
-    const int n = g.n;
-    const int64_t ld = g.ld;
-    const bool vec = ((reinterpret_cast<uintptr_t>(D) & 15u) == 0) && ((ld & 3) == 0);
-    const int I = it.ij >> 16, J = it.ij & 0xffff;
-    const int kb = r * T64, i0 = I * T64, j0 = J * T64;
-    const int kw = (n - kb) < T64 ? (n - kb) : T64;
-    const int mr = (n - i0) < T64 ? (n - i0) : T64;
-    const int nc = (n - j0) < T64 ? (n - j0) : T64;
-    uint32_t acc[4][4];
-    load64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
-    if (CLOSE_ONLY) {
-        close64<Op>(acc, kw, L);
-    } else {
-        update64<Op>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
-        if (I == r + 1 && J == r + 1)  // phase 1 of round r+1, fused
-            close64<Op>(acc, mr, L);
-    }
-    store64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
-}
-
-}  // namespace
-
-hipError_t launch_batched64_items(const BatchDesc *descs, const BatchItem *items,
-                                  const XcdRanges &ranges, int r, bool close_only, int dtype,
-                                  hipStream_t s) {
-    int longest = 0;
-    for (int x = 0; x < 8; ++x) longest = ranges.count[x] > longest ? ranges.count[x] : longest;
-    if (longest == 0) return hipSuccess;
-    const dim3 grid((unsigned)longest * 8u);
-    if (dtype == 0) {
-        if (close_only)
-            hipLaunchKernelGGL((k_batched64<OpI32, true>), grid, dim3(NT64), 0, s, descs, items, ranges, r);
-        else
-            hipLaunchKernelGGL((k_batched64<OpI32, false>), grid, dim3(NT64), 0, s, descs, items, ranges, r);
-    } else {
-        if (close_only)
-            hipLaunchKernelGGL((k_batched64<OpF32, true>), grid, dim3(NT64), 0, s, descs, items, ranges, r);
-        else
-            hipLaunchKernelGGL((k_batched64<OpF32, false>), grid, dim3(NT64), 0, s, descs, items, ranges, r);
-    }
-    return hipGetLastError();
-}
-
+}  // namespace tile64
 }  // namespace apsp

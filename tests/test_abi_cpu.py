@@ -140,6 +140,13 @@ def test_tiled_plan_and_tuning_argument_validation(lib):
     assert lib.apsp_batched_autotune(2, 1 << 24, None, None, None) == 1      # dtype
     assert lib.apsp_batched_autotune(0, 1 << 19, None, None, None) == 1      # batch too small
     assert lib.apsp_batched_autotune(0, (1 << 30) + 1, None, None, None) == 1
+    assert lib.apsp_batched_autotune_batch(ptrs, ns, None, 0, 0, None, None, None) == 1
+    assert lib.apsp_batched_autotune_batch(None, ns, None, 2, 0, None, None, None) == 1
+    assert lib.apsp_batched_autotune_batch(ptrs, ns, None, 2, 7, None, None, None) == 1
+    big = (ctypes.c_int32 * 2)(4, 5000)
+    assert lib.apsp_batched_autotune_batch(ptrs, big, None, 2, 0, None, None, None) == 1
+    empty = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.apsp_batched_autotune_batch(ptrs, empty, None, 2, 0, None, None, None) == 1
 
 
 def test_minplus_and_squaring_argument_validation(lib):

@@ -392,6 +392,40 @@ def test_batched_forced_width_int32_exact(apsp, dev, tile):
     plan.close()
 
 
+def _weighted_int(n, seed, wlo, whi, p=None, diag=0):
+    rng = gg.rng_for(gg.CFG_TEST, seed)
+    W = rng.integers(wlo, whi + 1, size=(n, n), dtype=np.int64)
+    W[rng.random((n, n)) > (p if p is not None else min(1.0, 6.0 / max(n, 1)))] = INF
+    np.fill_diagonal(W, diag)
+    return W.astype(np.int32)
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_batched_int32_fp32_pipe_boundary(apsp, dev, tile):
+    """int32 graphs run on the fp32 pipe only when 2 (n-1) wmax < 2^24; results
+    are exact on both sides of that bound, with saturation at 2^30."""
+    import torch
+
+    cases = [
+        (65, 131071, 0),            # 2*64*131071 = 2^24 - 128: fp32 pipe
+        (65, 131072, 0),            # 2*64*131072 = 2^24: uint32
+        (300, 1 << 21, 0),          # far above the bound: uint32
+        (200, 1000, 1 << 29),       # huge diagonal entries are not weights
+        (150, 1 << 29, 0),          # sums reach 2^30: saturate to "no edge"
+        (129, 1, 0),                # unit weights
+        (2, (1 << 30) - 1, 0),      # largest finite weight
+    ]
+    Ws = [_weighted_int(n, 1000 + i, max(1, whi // 2), whi, diag=d)
+          for i, (n, whi, d) in enumerate(cases)]
+    mats = [_to_dev(W, dev)[0] for W in Ws]
+    plan = apsp.BatchPlan(mats, tile=tile)
+    plan.run()
+    torch.cuda.synchronize()
+    for (n, whi, _), W, m in zip(cases, Ws, mats):
+        assert np.array_equal(m.cpu().numpy().astype(np.int64), oracle.fw(W)), (n, whi)
+    plan.close()
+
+
 def test_batched_width64_fp32_bitexact(apsp, dev):
     import torch
 
@@ -445,6 +479,27 @@ def test_batched_autotune(apsp, dev, default_tuning):
     # the tuned table is what plans now use, and results stay exact
     Ws = gg.batched_graphs(64, item=3)
     views = [torch.from_numpy(W).to(dev) for W in Ws]
+    apsp.solve_batched(views)
+    torch.cuda.synchronize()
+    for W, v in zip(Ws, views):
+        assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
+
+
+def test_batched_autotune_batch(apsp, dev, default_tuning):
+    """The whole-batch tuner reads the batch only, and plans built after it
+    use its table with exact results."""
+    import torch
+
+    Ws = gg.batched_graphs(256, item=5)
+    views = [torch.from_numpy(W).to(dev) for W in Ws]
+    before = [v.clone() for v in views]
+    res = apsp.batched_autotune_batch(views)
+    torch.cuda.synchronize()
+    print(f"batch autotune {res}")
+    assert all(torch.equal(a, b) for a, b in zip(before, views))
+    assert all(w in (64, 128) for w in res["widths"])
+    assert res["ms_all_128"] > 0 and 0 < res["ms_tuned"] <= res["ms_all_128"]
+    assert apsp.batched_tuning() == res["widths"]
     apsp.solve_batched(views)
     torch.cuda.synchronize()
     for W, v in zip(Ws, views):
