@@ -46,7 +46,10 @@ VALU_PEAK_UPD = CUS * CLOCK_HZ * UPDATES_PER_CLK_PER_CU   # 39.32e12 updates/s
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_04446_amd", "csrc", "apsp_plain.hip")
+# the phase-3 kernel and the schedule that launches it (the traffic figures
+# hold while these sources are unchanged)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_04446_amd", "csrc", f)
+                  for f in ("apsp_plain.hip", "apsp_tile.h", "apsp_runtime.hip")]
 
 
 def cell_updates_per_s(n: int, seconds: float) -> float:
@@ -103,7 +106,10 @@ def phase3_traffic() -> float | None:
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    src = h.hexdigest()
     if kv.get("kernel_source_sha256") != src:
         return None
     return float(kv["bytes_per_launch"])
@@ -365,6 +371,51 @@ def bench_variants(apsp, torch, dev, pristine, work, n: int, b: int) -> dict:
     return out
 
 
+def bench_stretch(apsp, torch, dev, rounds: int) -> dict:
+    """n = 262144 (a 256 GiB fp32 matrix, the paper's largest problem) on one GPU.
+
+    A full solve takes minutes, so the first rounds are timed and the solve
+    time is projected as rounds x the time of one: every round does the same
+    work (2(q-1) panel tiles and (q-1)^2 update tiles, n being a multiple of
+    128) and the kernels do not branch on the data.
+    """
+    import numpy as np
+
+    import graphgen as gg
+
+    n = 262144
+    need = n * n * 4
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        log(f"stretch: skipped, {free / 2**30:.0f} GiB free < {need / 2**30:.0f} GiB + 4 GiB")
+        return {"n": n, "skipped": f"{free / 2**30:.0f} GiB of device memory free"}
+    log(f"stretch: building Swiss-roll kNN graph n={n} (256 GiB matrix)")
+    u, v, w = gg.swiss_roll_knn(n, gg.CFG_SWISS_256K, 0)
+    D = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+    del u, v, w
+    b = apsp.round_width(n, apsp.APSP_F32)
+    q = -(-n // b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    apsp.solve_rounds(D, 0, 1)  # input normalisation + round 0 (warm-up)
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    apsp.solve_rounds(D, 1, 1 + rounds)
+    torch.cuda.synchronize()
+    t_rounds = time.perf_counter() - t0
+    del D
+    torch.cuda.empty_cache()
+    per_round = t_rounds / rounds
+    projected = per_round * q
+    log(f"stretch: round 0 {t_first * 1e3:.0f} ms, rounds 1..{rounds} {per_round * 1e3:.1f} ms "
+        f"each; projected solve {projected:.0f} s")
+    return {"n": n, "matrix_GiB": need / 2**30, "round_width": b, "rounds": q,
+            "rounds_timed": rounds, "ms_per_round": round(per_round * 1e3, 2),
+            "first_round_ms": round(t_first * 1e3, 2), "projected_solve_s": round(projected, 1),
+            "projected_T_cell_updates_per_s": round(float(n) ** 3 / projected / 1e12, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +430,8 @@ def main() -> int:
                     help="requests per serving run (0 disables the serving section)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--stretch-rounds", type=int, default=3,
+                    help="timed rounds of the n=262144 solve (0 disables it)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -433,7 +486,9 @@ def main() -> int:
     rest_upd, rest_launches = phase3_rest_updates(n, b)
     launches = phases["phase3_rest_launches"] / K
     if q >= 3 and launches == rest_launches:
-        kernel = "k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles)"
+        kernel = ("k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles; two "
+                  "concurrent launches per round, one per band of block rows; per-launch "
+                  "figures are per round)")
         launch_s = phases["phase3_rest"] / K / 1e3 / rest_launches
         per_launch = rest_upd / rest_launches
     else:  # no lookahead split at this size: whole phase 3 in one launch per round
@@ -466,6 +521,12 @@ def main() -> int:
     if args.serving > 0:
         serving = bench_serving(apsp, torch, dev, args.serving)
 
+    stretch = None
+    if args.stretch_rounds > 0:
+        del pristine, work
+        torch.cuda.empty_cache()
+        stretch = bench_stretch(apsp, torch, dev, args.stretch_rounds)
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(n, u, v, w, args.cpu_seconds)
@@ -493,6 +554,7 @@ def main() -> int:
         "variants": variants,
         "batched": batched,
         "serving": serving,
+        "stretch": stretch,
     }
     print(json.dumps(out), flush=True)
     return 0

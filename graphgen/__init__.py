@@ -31,6 +31,7 @@ CFG_SWISS_16K = 2        # Swiss-roll kNN, n=16384, fp32
 CFG_SWISS_64K = 3        # Swiss-roll kNN, n=65536, fp32
 CFG_BATCHED = 4          # 4096 ER graphs, n log-uniform in [32, 512], p=8/n
 CFG_SERVING = 5          # Poisson request stream, Swiss-roll kNN graphs
+CFG_SWISS_256K = 6       # Swiss-roll kNN, n=262144, fp32 (256 GiB matrix)
 CFG_TEST = 100           # ad-hoc test inputs
 
 

@@ -101,10 +101,12 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
  * launch; waits for the solve to finish, then writes into phase_ms[0..7]:
  *   [0] input normalisation (ms)
  *   [1] phase 1, summed over rounds        [2] phase 2, summed over rounds
- *   [3] phase 3, summed over its launches  [4] the whole solve
- *   [5] the phase-3 launches that run on the helper stream (all of phase 3
- *       except block row/column r+1), summed   [6] how many such launches
- *   [7] the other phase-3 launches, summed
+ *   [3] phase 3: [5] + [7]                 [4] the whole solve
+ *   [5] the time during which the phase-3 tiles outside block row/column
+ *       r+1 were being updated: they run as bands of block rows on helper
+ *       streams, bands of consecutive rounds overlapping, and [5] is the
+ *       union of those launches' intervals   [6] how many rounds had them
+ *   [7] the other phase-3 launches (block row/column r+1), summed
  * Phase-3 launches overlap phases 1 and 2 of the next round (one-round
  * lookahead), so [1] + [2] + [3] can exceed [4].  The result in `dist` is
  * identical to apsp_solve's.  phase_ms must have room for 8 values.

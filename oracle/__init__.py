@@ -18,6 +18,9 @@ Functions:
 ``fw``             classic Floyd-Warshall, Sec. 3 (Table 1 FloydWarshall)
 ``fw_steps``       the same loop stopped after pivots k0..k1-1 (the state a
                    blocked solver must reach after each round)
+``fw_prefix_rows`` rows of the state after pivots 0..K-1 from adjacency lists
+                   (paths with intermediates in the first K vertices), for
+                   sizes where no n x n matrix fits on the host
 ``dijkstra``       Dijkstra from the given sources (independent algorithm)
 ``brute``          minimum over all simple paths, n <= 10 (the definition)
 ``blocked``        three-phase blocked method, Sec. 4.4/4.5, Alg. 3/4, in the
@@ -71,6 +74,7 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
                                      ctypes.c_double),
         "orc_bellman_violations_i32": ([_p, _i64, _i64, _p, _p, _p, _p, _i64, ctypes.c_int],
                                        ctypes.c_int64),
+        "orc_fw_prefix_rows_f64": ([_p, _p, _p, _i64, _i64, _p, _i64, _p, ctypes.c_int], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -186,6 +190,24 @@ def dijkstra(csr, n: int, sources, threads: int = 1, integer: bool = False) -> n
         out = np.empty((src.size, n), np.float64)
         lib.orc_dijkstra_csr_f64(_ptr(indptr), _ptr(indices), _ptr(w), n, _ptr(src), src.size,
                                  _ptr(out), threads)
+    return out
+
+
+def fw_prefix_rows(csr, n: int, K: int, rows, threads: int = 1) -> np.ndarray:
+    """Rows of the Floyd-Warshall state after pivots 0..K-1, from adjacency lists.
+
+    ``csr`` = (indptr, indices, weights); the result (len(rows) x n, float64,
+    +inf = no path) equals those rows of ``fw_steps(prepare(W), 0, K)`` for
+    the matrix W the lists describe, without forming any n x n matrix.
+    """
+    lib = _lib()
+    indptr = np.ascontiguousarray(csr[0], np.int64)
+    indices = np.ascontiguousarray(csr[1], np.int64)
+    w = np.ascontiguousarray(csr[2], np.float64)
+    src = np.ascontiguousarray(np.asarray(rows, np.int64).ravel())
+    out = np.empty((src.size, n), np.float64)
+    lib.orc_fw_prefix_rows_f64(_ptr(indptr), _ptr(indices), _ptr(w), n, K, _ptr(src), src.size,
+                               _ptr(out), threads)
     return out
 
 

@@ -540,3 +540,74 @@ int64_t orc_bellman_violations_i32(const int32_t *D, int64_t ldd, int64_t n, con
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rows of the Floyd-Warshall state after the first K pivots (Sec. 3: the  */
+/* classic loop stopped after k = 0 .. K-1; a blocked solver reaches this   */
+/* state after K / b rounds), for a graph given as adjacency lists, so no   */
+/* n x n matrix is needed.  Entry (i, j) of that state is the least length  */
+/* over i -> j paths whose intermediate vertices all lie in {0 .. K-1}.     */
+/* Such a path is the edge (i, j) itself, or                                */
+/*     edge i -> a,  a shortest a -> b path inside {0 .. K-1},  edge b -> j */
+/* with a, b < K, where a = i (i < K) and b = j (j < K) stand for the      */
+/* empty first or last edge.  The a -> b lengths come from the classic      */
+/* loop on the subgraph induced by {0 .. K-1}.  fp64; +inf = no path.       */
+/* ------------------------------------------------------------------------ */
+void orc_fw_prefix_rows_f64(const int64_t *indptr, const int64_t *indices, const double *w,
+                            int64_t n, int64_t K, const int64_t *rows, int64_t nrows, double *out,
+                            int threads)
+{
+    if (threads < 1) threads = 1;
+    if (K > n) K = n;
+    double *dk = (double *)malloc(sizeof(double) * (size_t)(K * K + 1));
+    for (int64_t t = 0; t < K * K; ++t) dk[t] = INFINITY;
+    for (int64_t a = 0; a < K; ++a) {
+        dk[a * K + a] = 0.0;
+        for (int64_t e = indptr[a]; e < indptr[a + 1]; ++e) {
+            const int64_t b = indices[e];
+            if (b < K && b != a && w[e] < dk[a * K + b]) dk[a * K + b] = w[e];
+        }
+    }
+    for (int64_t k = 0; k < K; ++k)
+        for (int64_t a = 0; a < K; ++a) {
+            const double dak = dk[a * K + k];
+            for (int64_t b = 0; b < K; ++b) {
+                const double c = dak + dk[k * K + b];
+                if (c < dk[a * K + b]) dk[a * K + b] = c;
+            }
+        }
+#pragma omp parallel num_threads(threads)
+    {
+        double *tb = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < nrows; ++t) {
+            const int64_t i = rows[t];
+            double *o = out + t * n;
+            for (int64_t j = 0; j < n; ++j) o[j] = INFINITY;
+            o[i] = 0.0;
+            for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e)
+                if (indices[e] != i && w[e] < o[indices[e]]) o[indices[e]] = w[e];
+            /* tb[b]: least i -> b length with every vertex after i in {0..K-1} */
+            for (int64_t b = 0; b < K; ++b) tb[b] = (i < K) ? dk[i * K + b] : INFINITY;
+            for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
+                const int64_t a = indices[e];
+                if (a >= K || a == i) continue;
+                for (int64_t b = 0; b < K; ++b) {
+                    const double c = w[e] + dk[a * K + b];
+                    if (c < tb[b]) tb[b] = c;
+                }
+            }
+            for (int64_t b = 0; b < K; ++b) {
+                if (isinf(tb[b])) continue;
+                if (tb[b] < o[b]) o[b] = tb[b];
+                for (int64_t e = indptr[b]; e < indptr[b + 1]; ++e) {
+                    const int64_t j = indices[e];
+                    const double c = tb[b] + w[e];
+                    if (j != i && c < o[j]) o[j] = c;
+                }
+            }
+        }
+        free(tb);
+    }
+    free(dk);
+}

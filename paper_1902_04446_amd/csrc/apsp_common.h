@@ -127,6 +127,11 @@ hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t 
 // phase 1 of round r+1 on it before storing it.
 hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
                            hipStream_t s, bool close_next_diag = false);
+// Phase-3 tiles outside block rows/columns r, r+1 whose block row lies in
+// [lo, hi) (kRest restricted to a band of block rows), and their count.
+hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int64_t lo,
+                            int64_t hi, hipStream_t s);
+int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 int64_t num_rounds(int64_t n);
 int64_t tile_count(int64_t n, int64_t r, int set);
 hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,

@@ -136,7 +136,8 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 // ---------------------------------------------------------------------------
 template <class Op, int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(
-    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag) {
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
+    int row_lo, int row_hi) {
     __shared__ tile::Lds L;
 
     int I, J;
@@ -163,19 +164,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             I = tt < r ? tt : tt + 2;
         }
     } else {
-        // kAll: every block row/column but r; kRest: every one but r, r+1.
+        // kAll: every block row/column but r.  kRest: the block rows in
+        // [row_lo, row_hi) but r and r+1, every block column but r and r+1.
         // Workgroups are dealt round-robin to the 8 XCDs (wg % 8); give each
         // XCD a contiguous range of tiles so tiles sharing panel blocks share
         // that XCD's L2.
         const int skip = (MODE == kRest) ? 2 : 1;
         const int m = q - skip;
-        const int T = m * m;
+        const int rows = (MODE == kRest)
+                             ? row_hi - row_lo - (r >= row_lo && r < row_hi ? 1 : 0) -
+                                   (r + 1 >= row_lo && r + 1 < row_hi ? 1 : 0)
+                             : m;
+        const int T = rows * m;
         const int wg = blockIdx.x;
         const int x = wg & 7, s = wg >> 3;
         const int per = T >> 3, rem = T & 7;
         const int tile = x * per + (x < rem ? x : rem) + s;
         const int ti = tile / m, tj = tile - ti * m;
-        I = ti < r ? ti : ti + skip;
+        if (MODE == kRest) {
+            I = row_lo + ti;
+            if (r >= row_lo && I >= r) ++I;
+            if (r + 1 >= row_lo && I >= r + 1) ++I;
+        } else {
+            I = ti < r ? ti : ti + skip;
+        }
         J = tj < r ? tj : tj + skip;
     }
 
@@ -202,19 +214,19 @@ inline unsigned grid_rows(int64_t n) { return (unsigned)(n < 8192 ? n : 8192); }
 
 template <class Op>
 void launch_tiles(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec, int close,
-                  hipStream_t s, unsigned grid) {
+                  int lo, int hi, hipStream_t s, unsigned grid) {
     switch (set) {
     case kPanels:
-        hipLaunchKernelGGL((k_tiles<Op, kPanels>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        hipLaunchKernelGGL((k_tiles<Op, kPanels>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi);
         break;
     case kAll:
-        hipLaunchKernelGGL((k_tiles<Op, kAll>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        hipLaunchKernelGGL((k_tiles<Op, kAll>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi);
         break;
     case kNext:
-        hipLaunchKernelGGL((k_tiles<Op, kNext>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        hipLaunchKernelGGL((k_tiles<Op, kNext>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi);
         break;
     default:
-        hipLaunchKernelGGL((k_tiles<Op, kRest>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+        hipLaunchKernelGGL((k_tiles<Op, kRest>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi);
         break;
     }
 }
@@ -274,9 +286,29 @@ hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_
     const int vec = aligned16(D, ld) ? 1 : 0;
     const int close = (set == kNext && close_next_diag) ? 1 : 0;
     if (dtype == 0)
-        launch_tiles<OpI32>(set, D, n, ld, (int)r, q, vec, close, s, (unsigned)count);
+        launch_tiles<OpI32>(set, D, n, ld, (int)r, q, vec, close, 0, q, s, (unsigned)count);
     else
-        launch_tiles<OpF32>(set, D, n, ld, (int)r, q, vec, close, s, (unsigned)count);
+        launch_tiles<OpF32>(set, D, n, ld, (int)r, q, vec, close, 0, q, s, (unsigned)count);
+    return hipGetLastError();
+}
+
+int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
+    const int64_t q = num_rounds(n);
+    if (r < 0 || r + 1 >= q || lo >= hi) return 0;
+    const int64_t rows = hi - lo - (r >= lo && r < hi ? 1 : 0) - (r + 1 >= lo && r + 1 < hi ? 1 : 0);
+    return rows > 0 ? rows * (q - 2) : 0;
+}
+
+hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int64_t lo,
+                            int64_t hi, hipStream_t s) {
+    const int64_t count = rest_rows_count(n, r, lo, hi);
+    if (count <= 0) return hipSuccess;
+    const int q = (int)num_rounds(n);
+    const int vec = aligned16(D, ld) ? 1 : 0;
+    if (dtype == 0)
+        launch_tiles<OpI32>(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, s, (unsigned)count);
+    else
+        launch_tiles<OpF32>(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, s, (unsigned)count);
     return hipGetLastError();
 }
 

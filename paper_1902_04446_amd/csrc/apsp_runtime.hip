@@ -23,10 +23,16 @@
 //   * P1(r+1) and P2(r+1) write only row/column r+1 tiles (A(r)'s outputs)
 //     and read the diagonal block r+1; none of these is touched by B(r);
 //   * A(r+1) rewrites row/column r+2 tiles, which B(r) wrote, so S waits
-//     for B(r) first; B(r+1) follows B(r) in order on H.
+//     for B(r) first.
+// B(r) itself runs as bands of block rows on separate helper streams; band g
+// of round r+1 follows band g of round r on its stream and reads only the
+// panels of round r+1 and its own tiles, so it does not wait for the other
+// bands of B(r), except the band holding block row r: that row was the row
+// panel all bands of B(r) read, and round r+1 overwrites it.
 // The last round has no round r+1: its phase 3 runs whole on S after B(r-1).
 // The result is the same as running the three phases in order, bit for bit:
 // every tile sees the same operands in the same round.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -38,12 +44,20 @@ namespace apsp {
 
 namespace {
 
+// B(r) is split into kBands bands of block rows, each on its own helper
+// stream: band g of round r+1 follows band g of round r and needs nothing
+// else of B(r), so one band's launch boundary overlaps the other band's work
+// instead of draining the GPU once per round.
+constexpr int kBands = 2;
+
 struct Helper {
-    hipStream_t side = nullptr;
-    hipEvent_t p2_done = nullptr;    // recorded on S after P2(r)
-    hipEvent_t rest_done = nullptr;  // recorded on H after B(r)
-    std::mutex mu;                   // one solve enqueues on this pair at a time
+    hipStream_t side[kBands] = {};
+    hipEvent_t p2_done = nullptr;             // recorded on S after P2(r)
+    hipEvent_t rest_done[kBands] = {};        // recorded on H_g after band g of B(r)
+    std::mutex mu;                            // one solve enqueues on these at a time
 };
+
+
 
 std::mutex g_map_mu;
 std::map<std::pair<int, hipStream_t>, Helper *> g_helpers;
@@ -63,12 +77,14 @@ Helper *helper_for(hipStream_t s, hipError_t *err) {
     if (it != g_helpers.end()) return it->second;
     Helper *h = new Helper();
     const char *what = "hipStreamCreateWithFlags";
-    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    for (int g = 0; g < kBands && e == hipSuccess; ++g)
+        e = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking);
     if (e == hipSuccess) {
         what = "hipEventCreateWithFlags";
         e = hipEventCreateWithFlags(&h->p2_done, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->rest_done, hipEventDisableTiming);
+    for (int g = 0; g < kBands && e == hipSuccess; ++g)
+        e = hipEventCreateWithFlags(&h->rest_done[g], hipEventDisableTiming);
     if (e != hipSuccess) {
         note_error(what, e);
         *err = e;
@@ -115,6 +131,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     // Lookahead needs a round r+1 with a non-empty rest set.
     const bool lookahead = q >= 3;
+    const int bands = kBands;
     hipError_t herr = hipSuccess;
     Helper *h = lookahead ? helper_for(s, &herr) : nullptr;
     if (lookahead && !h) return herr;
@@ -123,7 +140,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     Timer tm;
     struct RoundEv {
-        hipEvent_t start, p1, p2, a0, a1, b0, b1;
+        hipEvent_t start, p1, p2, a0, a1, b0[kBands], b1[kBands];
     };
     std::vector<RoundEv> rev;
     hipEvent_t t_begin = nullptr, t_pro = nullptr, t_end = nullptr;
@@ -137,7 +154,11 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         rev.resize((size_t)(r1 - r0));
         for (auto &e : rev) {
             e.start = tm.make(); e.p1 = tm.make(); e.p2 = tm.make();
-            e.a0 = tm.make(); e.a1 = tm.make(); e.b0 = tm.make(); e.b1 = tm.make();
+            e.a0 = tm.make(); e.a1 = tm.make();
+            for (int g = 0; g < kBands; ++g) {
+                e.b0[g] = tm.make();
+                e.b1[g] = tm.make();
+            }
         }
         if (!tm.ok) return hipErrorOutOfMemory;
         rec(t_begin, s);
@@ -169,26 +190,42 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             // Floyd-Warshall after its last round's pivots.
             const bool fuse = r + 1 < r1;
             chk(hipEventRecord(h->p2_done, s));
-            if (rest_pending) chk(hipStreamWaitEvent(s, h->rest_done, 0));
+            if (rest_pending)
+                for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
             if (e) rec(e->a0, s);
             chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse));
             if (e) rec(e->a1, s);
             diag_closed = fuse;
-            chk(hipStreamWaitEvent(h->side, h->p2_done, 0));
-            if (e) rec(e->b0, h->side);
-            chk(launch_tile_set(D, n, ld, dtype, r, kRest, h->side));
-            if (e) rec(e->b1, h->side);
-            chk(hipEventRecord(h->rest_done, h->side));
+            for (int g = 0; g < bands; ++g) {
+                // band g: block rows [q g / bands, q (g+1) / bands)
+                const int64_t lo = q * g / bands, hi = q * (g + 1) / bands;
+                // Block row r-1 was the row panel every band of B(r-1) read;
+                // the band that now updates it waits for all of B(r-1).  (The
+                // events still hold round r-1: this round records them below.)
+                if (rest_pending && r - 1 >= lo && r - 1 < hi)
+                    for (int o = 0; o < bands; ++o)
+                        if (o != g) chk(hipStreamWaitEvent(h->side[g], h->rest_done[o], 0));
+            }
+            for (int g = 0; g < bands; ++g) {
+                const int64_t lo = q * g / bands, hi = q * (g + 1) / bands;
+                chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
+                if (e) rec(e->b0[g], h->side[g]);
+                chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g]));
+                if (e) rec(e->b1[g], h->side[g]);
+                chk(hipEventRecord(h->rest_done[g], h->side[g]));
+            }
             rest_pending = true;
         } else {
-            if (rest_pending) chk(hipStreamWaitEvent(s, h->rest_done, 0));
+            if (rest_pending)
+                for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
             rest_pending = false;
             if (e) rec(e->a0, s);
             chk(launch_tile_set(D, n, ld, dtype, r, kAll, s));
             if (e) rec(e->a1, s);
         }
     }
-    if (rest_pending) chk(hipStreamWaitEvent(s, h->rest_done, 0));
+    if (rest_pending)
+        for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
     if (err != hipSuccess) return err;
     if (!times) return hipSuccess;
 
@@ -197,20 +234,34 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     if ((err = hipEventSynchronize(t_end)) != hipSuccess) return err;
     double *m = times->ms;
     m[0] = elapsed(t_begin, t_pro);
+    // B: the time during which any band of any round ran (the union of the
+    // band launches' intervals; bands of consecutive rounds overlap)
+    std::vector<std::pair<double, double>> spans;
     for (int64_t r = r0; r < r1; ++r) {
         const RoundEv &e = rev[(size_t)(r - r0)];
         m[1] += elapsed(e.start, e.p1);
         m[2] += elapsed(e.p1, e.p2);
-        const double a = elapsed(e.a0, e.a1);
-        const bool split = lookahead && r + 1 < q;
-        const double b = split ? elapsed(e.b0, e.b1) : 0.0;
-        m[3] += a + b;
-        if (split) {
-            m[5] += b;
+        m[7] += elapsed(e.a0, e.a1);
+        if (lookahead && r + 1 < q) {
+            for (int g = 0; g < bands; ++g)
+                spans.emplace_back(elapsed(t_begin, e.b0[g]), elapsed(t_begin, e.b1[g]));
             m[6] += 1.0;
         }
-        m[7] += a;
     }
+    std::sort(spans.begin(), spans.end());
+    double cover = 0.0, lo = 0.0, hi = -1.0;
+    for (const auto &sp : spans) {
+        if (sp.first > hi) {
+            if (hi > lo) cover += hi - lo;
+            lo = sp.first;
+            hi = sp.second;
+        } else if (sp.second > hi) {
+            hi = sp.second;
+        }
+    }
+    if (hi > lo) cover += hi - lo;
+    m[5] = cover;
+    m[3] = m[7] + cover;
     m[4] = elapsed(t_begin, t_end);
     return hipSuccess;
 }

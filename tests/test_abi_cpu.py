@@ -214,6 +214,28 @@ def _phase3_tile(wg, r, q, skip=1):
     return (ti if ti < r else ti + skip), (tj if tj < r else tj + skip)
 
 
+def _rest_band_tile(wg, r, q, lo, hi):
+    # phase-3 tiles outside rows/columns r, r+1 whose block row is in [lo, hi)
+    m = q - 2
+    rows = hi - lo - (lo <= r < hi) - (lo <= r + 1 < hi)
+    T = rows * m
+    x, s = wg & 7, wg >> 3
+    per, rem = T >> 3, T & 7
+    tile = x * per + min(x, rem) + s
+    ti, tj = divmod(tile, m)
+    i = lo + ti
+    if r >= lo and i >= r:
+        i += 1
+    if r + 1 >= lo and i >= r + 1:
+        i += 1
+    return i, (tj if tj < r else tj + 2)
+
+
+def _band_count(r, q, lo, hi):
+    rows = hi - lo - (lo <= r < hi) - (lo <= r + 1 < hi)
+    return max(rows, 0) * (q - 2) if r + 1 < q else 0
+
+
 def _next_tile(wg, r, q):
     # block row r+1 (all columns but r), then block column r+1 (rows but r, r+1)
     if wg < q - 1:
@@ -242,3 +264,16 @@ def test_phase_tile_maps_are_bijections(q):
             assert len(set(nxt)) == len(nxt) and len(set(rest)) == len(rest)
             assert set(nxt) | set(rest) == expect3 and not set(nxt) & set(rest)
             assert set(nxt) == {t for t in expect3 if r + 1 in t}
+            # the rest set split in bands of block rows: disjoint, covering it,
+            # the full band [0, q) being the rest set itself
+            full = [_rest_band_tile(w, r, q, 0, q) for w in range(_band_count(r, q, 0, q))]
+            assert full == rest
+            for bands in (2, 3):
+                got = []
+                for g in range(bands):
+                    lo, hi = q * g // bands, q * (g + 1) // bands
+                    band = [_rest_band_tile(w, r, q, lo, hi)
+                            for w in range(_band_count(r, q, lo, hi))]
+                    assert all(lo <= i < hi for i, _ in band)
+                    got += band
+                assert len(got) == len(set(got)) and set(got) == set(rest)

@@ -228,6 +228,36 @@ def test_blocked_round_state_matches_fw_prefix(n, b):
         assert np.array_equal(state.astype(np.int64), np.minimum(fw_state, INF))
 
 
+@pytest.mark.parametrize("n,K", [(1, 0), (1, 1), (60, 0), (60, 1), (120, 17), (150, 64),
+                                 (97, 97), (200, 300)])
+def test_fw_prefix_rows_match_stopped_loop(n, K):
+    # Rows of the state after pivots 0..K-1, built from adjacency lists by
+    # splitting paths at their first and last intermediate vertex, equal the
+    # classic loop stopped after K pivots (different algorithm, same state).
+    W, (u, v, w) = _rand_int_graph(n, 0.05, 1, 100, 3000 + n + K)
+    fw_state = np.minimum(oracle.fw_steps(oracle.prepare(W), 0, min(K, n)), INF)
+    csr = gg.csr_from_edges(n, u, v, w)
+    rows = np.arange(n)
+    P = oracle.fw_prefix_rows(csr, n, K, rows, threads=4)
+    assert np.array_equal(np.where(np.isinf(P), INF, P).astype(np.int64), fw_state)
+
+
+def test_fw_prefix_rows_directed_and_full():
+    # directed adjacency lists; K = n is the full solve (Dijkstra)
+    n = 140
+    rng = gg.rng_for(gg.CFG_TEST, 3100)
+    W = rng.integers(1, 60, size=(n, n)).astype(np.int32)
+    W[rng.random((n, n)) > 0.04] = INF
+    csr = oracle.csr_from_dense(W)
+    for K in (0, 5, 70):
+        P = oracle.fw_prefix_rows(csr, n, K, np.arange(n))
+        ref = np.minimum(oracle.fw_steps(oracle.prepare(W), 0, K), INF)
+        assert np.array_equal(np.where(np.isinf(P), INF, P).astype(np.int64), ref), K
+    P = oracle.fw_prefix_rows(csr, n, n, [0, 7, 139])
+    D = oracle.dijkstra(csr, n, [0, 7, 139], integer=True)
+    assert np.array_equal(np.where(np.isinf(P), INF, P).astype(np.int64), D)
+
+
 def test_minplus_matches_definition():
     rng = gg.rng_for(gg.CFG_TEST, 42)
     A = rng.random((13, 7)).astype(np.float32)
