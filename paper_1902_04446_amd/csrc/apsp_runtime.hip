@@ -49,6 +49,12 @@ namespace {
 // else of B(r), so one band's launch boundary overlaps the other band's work
 // instead of draining the GPU once per round.
 constexpr int kBands = 2;
+// Below this many rounds a band launch is too short for the overlap to pay
+// for the extra launch and event per round; B(r) then runs as one launch.
+#ifndef APSP_MIN_BAND_ROUNDS
+#define APSP_MIN_BAND_ROUNDS 64
+#endif
+constexpr int64_t kMinBandRounds = APSP_MIN_BAND_ROUNDS;
 
 struct Helper {
     hipStream_t side[kBands] = {};
@@ -131,7 +137,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     // Lookahead needs a round r+1 with a non-empty rest set.
     const bool lookahead = q >= 3;
-    const int bands = kBands;
+    const int bands = q >= kMinBandRounds ? kBands : 1;
     hipError_t herr = hipSuccess;
     Helper *h = lookahead ? helper_for(s, &herr) : nullptr;
     if (lookahead && !h) return herr;
