@@ -485,6 +485,43 @@ def test_batched_autotune(apsp, dev, default_tuning):
         assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.fw(W)), W.shape
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_batched_plan_in_hip_graph(apsp, dev, dtype):
+    """A plan's run() only launches kernels, so it can be captured in a HIP
+    graph; every replay (with eager resets between them) gives the eager result."""
+    import torch
+
+    sizes = [40, 64, 130, 257, 300]
+    if dtype == np.int32:
+        Ws = [_directed_int(n, 1200 + n) for n in sizes]
+    else:
+        Ws = [_swiss(n, 1300 + n)[0] for n in sizes]
+    pristine = [torch.from_numpy(W).to(dev) for W in Ws]
+    mats = [p.clone() for p in pristine]
+    plan = apsp.BatchPlan(mats)
+    plan.run()
+    torch.cuda.synchronize()
+    expect = [m.clone() for m in mats]
+    for W, e in zip(Ws, expect):
+        ref = oracle.fw(W) if dtype == np.int32 else oracle.blocked(W, apsp.batched_round_width(W.shape[0], 1))
+        assert np.array_equal(e.cpu().numpy().astype(ref.dtype), ref)
+    for m, p in zip(mats, pristine):
+        m.copy_(p)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run()
+    for rep in range(3):
+        for m, p in zip(mats, pristine):
+            m.copy_(p)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for m, e in zip(mats, expect):
+            assert torch.equal(m, e), rep
+    plan.close()
+
+
 def test_batched_autotune_batch(apsp, dev, default_tuning):
     """The whole-batch tuner reads the batch only, and plans built after it
     use its table with exact results."""
