@@ -141,7 +141,7 @@ def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
                       f"{n / k * dt:.0f} s"}
 
 
-def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
+def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True) -> dict:
     """Many small graphs: one batched launch vs a loop of single-graph solves.
 
     4096 ER graphs, n log-uniform in [32, 512], p = 8/n, int32 U{1..1000}.
@@ -209,8 +209,10 @@ def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
         for w_ in work:
             apsp.solve(w_)
 
-    t_loop = timed(loop)
-    same = same and same_as(ref)
+    t_loop = float("nan")
+    if loop_too:
+        t_loop = timed(loop)
+        same = same and same_as(ref)
     log(f"batched: tuned plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches); "
         f"width 128 only {fixed[128][0] * 1e3:.2f} ms, width 64 only {fixed[64][0] * 1e3:.2f} ms; "
         f"one-shot call {t_oneshot * 1e3:.2f} ms, per-graph loop {t_loop * 1e3:.2f} ms, "
@@ -224,10 +226,12 @@ def bench_batched(apsp, torch, dev, count: int, reps: int) -> dict:
             "width128_only_ms": round(fixed[128][0] * 1e3, 3),
             "width64_only_ms": round(fixed[64][0] * 1e3, 3),
             "oneshot_call_ms": round(t_oneshot * 1e3, 3),
-            "plain_loop_ms": round(t_loop * 1e3, 3),
+            "plain_loop_ms": round(t_loop * 1e3, 3) if loop_too else None,
             "batched_T_cell_updates_per_s": round(sum_n3 / t_batched / 1e12, 3),
-            "plain_loop_T_cell_updates_per_s": round(sum_n3 / t_loop / 1e12, 3),
-            "speedup": round(t_loop / t_batched, 2), "bit_identical": bool(same)}
+            "plain_loop_T_cell_updates_per_s":
+                round(sum_n3 / t_loop / 1e12, 3) if loop_too else None,
+            "speedup": round(t_loop / t_batched, 2) if loop_too else None,
+            "bit_identical": bool(same)}
 
 
 def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2)) -> dict:
@@ -430,6 +434,8 @@ def main() -> int:
                     help="requests per serving run (0 disables the serving section)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--batched-loop", type=int, default=1,
+                    help="also time the batch as a loop of single-graph solves (0 skips it)")
     ap.add_argument("--stretch-rounds", type=int, default=3,
                     help="timed rounds of the n=262144 solve (0 disables it)")
     args = ap.parse_args()
@@ -515,7 +521,8 @@ def main() -> int:
 
     batched = None
     if args.batched > 0:
-        batched = bench_batched(apsp, torch, dev, args.batched, reps=3)
+        batched = bench_batched(apsp, torch, dev, args.batched, reps=3,
+                                loop_too=bool(args.batched_loop))
 
     serving = None
     if args.serving > 0:
