@@ -113,6 +113,24 @@ def swiss_roll_knn(n: int, config_id: int, item_id: int = 0, k: int = 10, sigma:
 # Dense adjacency matrices and CSR lists
 # --------------------------------------------------------------------------
 
+def with_hub_edges(n: int, u, v, w, K: int, rng: np.random.Generator):
+    """The edges (u, v, w) plus a star from vertex 0 to vertices 1..K-1 and an
+    edge from every vertex j >= K to vertex j % K, weights U[0.5, 1.5) fp32,
+    dropping those that duplicate an existing edge.  After the first K
+    pivots of Floyd-Warshall every pair is then joined by a path of a few
+    hops, so every entry of the matrix holds a finite length."""
+    j = np.arange(K, n, dtype=np.int64)
+    hu = np.concatenate([np.zeros(K - 1, dtype=np.int64), j])
+    hv = np.concatenate([np.arange(1, K, dtype=np.int64), j % K])
+    hw = rng.uniform(0.5, 1.5, size=hu.size).astype(np.float32)
+    u, v = np.asarray(u, np.int64), np.asarray(v, np.int64)
+    key = np.minimum(u, v) * n + np.maximum(u, v)
+    hkey = np.minimum(hu, hv) * n + np.maximum(hu, hv)
+    keep = ~np.isin(hkey, key)
+    return (np.concatenate([u, hu[keep]]), np.concatenate([v, hv[keep]]),
+            np.concatenate([np.asarray(w, np.float32), hw[keep]]))
+
+
 def dense_from_edges(n: int, u, v, w, dtype, ld: int | None = None) -> np.ndarray:
     """Dense n x n (row-major, leading dimension ``ld``) adjacency matrix.
 

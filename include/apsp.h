@@ -72,10 +72,16 @@ enum {
  *   ld     leading dimension in elements, ld >= max(n, 1).
  *   dtype  APSP_I32 or APSP_F32.
  *   stream hipStream_t to enqueue on (NULL = default stream).
- * Needs no device memory beyond `dist`.  For n > 256 the phases of round
- * r+1 overlap the bulk of round r's phase 3 on a library-owned helper stream
- * (one per device and caller stream, created on first use and kept); the
- * call makes `stream` wait for that work, so stream order is preserved.
+ * For n > 256 the phases of round r+1 overlap the bulk of round r's phase 3
+ * on library-owned helper streams (one set per device and caller stream,
+ * created on first use and kept; from 64 rounds up that phase 3 runs as two
+ * bands of block rows on two of them); the call makes `stream` wait for that
+ * work, so stream order is preserved.  int32 matrices are first scanned for
+ * their largest finite entry w; when 2 (n-1) w < 2^24 every sum the method
+ * forms is an integer below 2^24, and the tiles are computed in fp32
+ * arithmetic (exact, so the result is the same) at its higher issue rate.
+ * The scan's result lives in a 256-byte device word allocated with the
+ * helper streams.  Nothing else is allocated.
  * Solves enqueued on the same stream from several host threads are
  * serialised by the library.
  * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY (helper stream

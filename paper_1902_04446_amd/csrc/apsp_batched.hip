@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int I = it.ij >> 16, J = it.ij & 0xffff;
     if (DT == 1)
         any_item<OpF32, CLOSE_ONLY>(g, vec, I, J, r, lds);
-    else if (batched_exact_f32(g.n, wmax[it.graph]))
+    else if (int_exact_in_f32(g.n, wmax[it.graph]))
         any_item<OpI32F, CLOSE_ONLY>(g, vec, I, J, r, lds);
     else
         any_item<OpI32, CLOSE_ONLY>(g, vec, I, J, r, lds);

@@ -60,7 +60,10 @@ struct OpF32 {
 //    integer below 2^24.  Every value the blocked method stores is the length
 //    of a shortest path over some subset of intermediate vertices, so at most
 //    (n-1) * wmax for the largest finite weight wmax, and every sum it forms
-//    adds two of them: 2 (n-1) wmax < 2^24 is sufficient (batched_exact_f32).
+//    adds two of them: 2 (n-1) wmax < 2^24 is sufficient (int_exact_in_f32).
+//    The same holds when a solve resumes from a partial state, with wmax the
+//    largest finite entry of that state: the remaining rounds compute shortest
+//    paths over subsets of intermediate vertices of the graph it describes.
 //    fp32 adds issue at a higher rate than uint32 adds on this VALU.
 struct OpI32F {
     static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) {
@@ -81,9 +84,9 @@ struct OpI32F {
     }
 };
 
-// Whether a graph of n vertices whose largest finite off-diagonal weight is
+// Whether a graph of n vertices whose largest finite off-diagonal entry is
 // wmax may take the OpI32F path bit-exactly: 2 (n-1) wmax < 2^24.
-__host__ __device__ __forceinline__ bool batched_exact_f32(int64_t n, uint32_t wmax) {
+__host__ __device__ __forceinline__ bool int_exact_in_f32(int64_t n, uint32_t wmax) {
     return n <= 1 || (uint64_t)2 * (uint64_t)(n - 1) * wmax < (1u << 24);
 }
 
@@ -125,12 +128,17 @@ hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStr
 hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s);
 // close_next_diag (kNext only): the workgroup of diagonal block r+1 also runs
 // phase 1 of round r+1 on it before storing it.
+// wmax (int32 only): the word launch_wmax filled for this matrix; int32 tiles
+// then run on the fp32 pipe when int_exact_in_f32(n, *wmax), else in uint32.
 hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
-                           hipStream_t s, bool close_next_diag = false);
+                           hipStream_t s, bool close_next_diag = false,
+                           const uint32_t *wmax = nullptr);
+// *wmax = largest finite (< 2^30) off-diagonal entry of the int32 matrix.
+hipError_t launch_wmax(const uint32_t *D, int64_t n, int64_t ld, uint32_t *wmax, hipStream_t s);
 // Phase-3 tiles outside block rows/columns r, r+1 whose block row lies in
 // [lo, hi) (kRest restricted to a band of block rows), and their count.
 hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int64_t lo,
-                            int64_t hi, hipStream_t s);
+                            int64_t hi, hipStream_t s, const uint32_t *wmax = nullptr);
 int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 int64_t num_rounds(int64_t n);
 int64_t tile_count(int64_t n, int64_t r, int set);

@@ -19,6 +19,8 @@
 // Precision: every candidate path length is one fp32 (or uint32) addition and
 // the minimum is exact, so the result of a phase does not depend on the order
 // in which k is visited within it.
+#include <algorithm>
+
 #include "apsp_tile.h"
 
 namespace apsp {
@@ -134,13 +136,8 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 // selects the tile set of the launch (apsp_common.h); the workgroup -> tile
 // maps are bijections onto each set.
 // ---------------------------------------------------------------------------
-template <class Op, int MODE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(
-    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
-    int row_lo, int row_hi) {
-    __shared__ tile::Lds L;
-
-    int I, J;
+template <int MODE>
+__device__ __forceinline__ void tile_of(int r, int q, int row_lo, int row_hi, int &I, int &J) {
     if (MODE == kPanels) {
         int tt = blockIdx.x;
         if (tt < q - 1) {
@@ -190,15 +187,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         }
         J = tj < r ? tj : tj + skip;
     }
+}
 
+// NORM converts on load and store (OpI32F: int32 storage, fp32 arithmetic).
+template <class Op, int MODE, bool NORM>
+__device__ __forceinline__ void tile_update(uint32_t *D, int64_t ld, int64_t n, int r, int I,
+                                            int J, bool vec, bool close_diag, tile::Lds &L) {
     const int64_t i0 = (int64_t)I * TB, j0 = (int64_t)J * TB, kb = (int64_t)r * TB;
     const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
     const int mr = (int)((n - i0) < TB ? (n - i0) : TB);
     const int nc = (int)((n - j0) < TB ? (n - j0) : TB);
 
     uint32_t acc[8][8];
-    tile::load_acc<Op, false>(acc, D, ld, i0, j0, mr, nc, vec);
-    tile::minplus_tile<Op, false>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
+    tile::load_acc<Op, NORM>(acc, D, ld, i0, j0, mr, nc, vec);
+    tile::minplus_tile<Op, NORM>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
     // Phase 1 of round r+1, fused: the workgroup that just produced diagonal
     // block r+1 closes it in registers before storing it.
     if (MODE == kNext && close_diag && I == r + 1 && J == r + 1)
@@ -206,11 +208,82 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     tile::store_acc<Op>(acc, D, ld, i0, j0, mr, nc, vec);
 }
 
+template <class Op, int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_tiles(
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
+    int row_lo, int row_hi) {
+    __shared__ tile::Lds L;
+    int I, J;
+    tile_of<MODE>(r, q, row_lo, row_hi, I, J);
+    tile_update<Op, MODE, false>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+}
+
+// int32: on the fp32 pipe (OpI32F, bit-identical) when the matrix's largest
+// finite entry *wmax allows it, else in uint32.
+template <int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_tiles_i32(
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
+    int row_lo, int row_hi, const uint32_t *__restrict__ wmax) {
+    __shared__ tile::Lds L;
+    int I, J;
+    tile_of<MODE>(r, q, row_lo, row_hi, I, J);
+    if (int_exact_in_f32(n, *wmax))
+        tile_update<OpI32F, MODE, true>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+    else
+        tile_update<OpI32, MODE, false>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+}
+
+__global__ void k_zero_word(uint32_t *w) { *w = 0u; }
+
+// *wmax = max(*wmax, largest finite off-diagonal entry): thread = column,
+// rows strided by the grid's y extent; one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_wmax(const uint32_t *__restrict__ D, int64_t n,
+                                              int64_t ld, uint32_t *wmax) {
+    __shared__ uint32_t part[4];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t m = 0;
+    if (j < n)
+        for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+            const uint32_t v = D[i * ld + j];
+            if (v < kInfI32 && i != j && v > m) m = v;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = part[0];
+        for (int w = 1; w < 4; ++w) m = part[w] > m ? part[w] : m;
+        if (m > 0) atomicMax(wmax, m);
+    }
+}
+
 inline bool aligned16(const void *p, int64_t ld) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && (ld & 3) == 0;
 }
 
 inline unsigned grid_rows(int64_t n) { return (unsigned)(n < 8192 ? n : 8192); }
+
+void launch_tiles_i32(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec,
+                      int close, int lo, int hi, const uint32_t *wmax, hipStream_t s,
+                      unsigned grid) {
+    switch (set) {
+    case kPanels:
+        hipLaunchKernelGGL((k_tiles_i32<kPanels>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        break;
+    case kAll:
+        hipLaunchKernelGGL((k_tiles_i32<kAll>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        break;
+    case kNext:
+        hipLaunchKernelGGL((k_tiles_i32<kNext>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        break;
+    default:
+        hipLaunchKernelGGL((k_tiles_i32<kRest>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        break;
+    }
+}
 
 template <class Op>
 void launch_tiles(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec, int close,
@@ -279,16 +352,29 @@ hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t 
 }
 
 hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
-                           hipStream_t s, bool close_next_diag) {
+                           hipStream_t s, bool close_next_diag, const uint32_t *wmax) {
     const int64_t count = tile_count(n, r, set);
     if (count <= 0) return hipSuccess;
     const int q = (int)num_rounds(n);
     const int vec = aligned16(D, ld) ? 1 : 0;
     const int close = (set == kNext && close_next_diag) ? 1 : 0;
-    if (dtype == 0)
+    if (dtype == 0 && wmax)
+        launch_tiles_i32(set, D, n, ld, (int)r, q, vec, close, 0, q, wmax, s, (unsigned)count);
+    else if (dtype == 0)
         launch_tiles<OpI32>(set, D, n, ld, (int)r, q, vec, close, 0, q, s, (unsigned)count);
     else
         launch_tiles<OpF32>(set, D, n, ld, (int)r, q, vec, close, 0, q, s, (unsigned)count);
+    return hipGetLastError();
+}
+
+hipError_t launch_wmax(const uint32_t *D, int64_t n, int64_t ld, uint32_t *wmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, wmax);
+    if (n > 0) {
+        // about 4096 workgroups, so about as many atomics on the one word
+        const unsigned gx = (unsigned)((n + 255) / 256);
+        const unsigned gy = gx >= 4096 ? 1u : (unsigned)std::min<int64_t>(4096 / gx, n);
+        hipLaunchKernelGGL(k_wmax, dim3(gx, gy), dim3(256), 0, s, D, n, ld, wmax);
+    }
     return hipGetLastError();
 }
 
@@ -300,12 +386,15 @@ int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
 }
 
 hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int64_t lo,
-                            int64_t hi, hipStream_t s) {
+                            int64_t hi, hipStream_t s, const uint32_t *wmax) {
     const int64_t count = rest_rows_count(n, r, lo, hi);
     if (count <= 0) return hipSuccess;
     const int q = (int)num_rounds(n);
     const int vec = aligned16(D, ld) ? 1 : 0;
-    if (dtype == 0)
+    if (dtype == 0 && wmax)
+        launch_tiles_i32(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, wmax, s,
+                         (unsigned)count);
+    else if (dtype == 0)
         launch_tiles<OpI32>(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, s, (unsigned)count);
     else
         launch_tiles<OpF32>(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, s, (unsigned)count);

@@ -60,6 +60,7 @@ struct Helper {
     hipStream_t side[kBands] = {};
     hipEvent_t p2_done = nullptr;             // recorded on S after P2(r)
     hipEvent_t rest_done[kBands] = {};        // recorded on H_g after band g of B(r)
+    uint32_t *word = nullptr;                 // int32: largest finite entry of the matrix
     std::mutex mu;                            // one solve enqueues on these at a time
 };
 
@@ -91,6 +92,10 @@ Helper *helper_for(hipStream_t s, hipError_t *err) {
     }
     for (int g = 0; g < kBands && e == hipSuccess; ++g)
         e = hipEventCreateWithFlags(&h->rest_done[g], hipEventDisableTiming);
+    if (e == hipSuccess) {
+        what = "hipMalloc";
+        e = hipMalloc(reinterpret_cast<void **>(&h->word), 256);
+    }
     if (e != hipSuccess) {
         note_error(what, e);
         *err = e;
@@ -139,8 +144,10 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     const bool lookahead = q >= 3;
     const int bands = q >= kMinBandRounds ? kBands : 1;
     hipError_t herr = hipSuccess;
-    Helper *h = lookahead ? helper_for(s, &herr) : nullptr;
-    if (lookahead && !h) return herr;
+    Helper *h = (lookahead || dtype == 0) ? helper_for(s, &herr) : nullptr;
+    if ((lookahead || dtype == 0) && !h) return herr;
+    // int32: the tiles take the fp32 pipe when this matrix allows it exactly
+    const uint32_t *wmax = dtype == 0 ? h->word : nullptr;
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
 
@@ -178,6 +185,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         }
     };
     if (prologue) chk(launch_prologue(D, n, ld, dtype, s));
+    if (wmax) chk(launch_wmax(D, n, ld, h->word, s));
     if (times) rec(t_pro, s);
 
     bool rest_pending = false;
@@ -188,7 +196,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         if (!diag_closed) chk(launch_phase1(D, n, ld, dtype, r, s));
         diag_closed = false;
         if (e) rec(e->p1, s);
-        chk(launch_tile_set(D, n, ld, dtype, r, kPanels, s));
+        chk(launch_tile_set(D, n, ld, dtype, r, kPanels, s, false, wmax));
         if (e) rec(e->p2, s);
         if (lookahead && r + 1 < q) {
             // Fuse phase 1 of round r+1 into A(r) unless this call stops after
@@ -199,7 +207,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             if (rest_pending)
                 for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
             if (e) rec(e->a0, s);
-            chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse));
+            chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse, wmax));
             if (e) rec(e->a1, s);
             diag_closed = fuse;
             for (int g = 0; g < bands; ++g) {
@@ -216,7 +224,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 const int64_t lo = q * g / bands, hi = q * (g + 1) / bands;
                 chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                 if (e) rec(e->b0[g], h->side[g]);
-                chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g]));
+                chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g], wmax));
                 if (e) rec(e->b1[g], h->side[g]);
                 chk(hipEventRecord(h->rest_done[g], h->side[g]));
             }
@@ -226,7 +234,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
             rest_pending = false;
             if (e) rec(e->a0, s);
-            chk(launch_tile_set(D, n, ld, dtype, r, kAll, s));
+            chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
             if (e) rec(e->a1, s);
         }
     }

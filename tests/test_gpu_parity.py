@@ -286,6 +286,53 @@ def test_full_size_swiss_65536(apsp, dev):
     print(f"n=65536 fp32: max rel err vs fp64 Dijkstra on sampled rows {worst:.3e}")
 
 
+@pytest.mark.parametrize("n,whi,diag", [
+    (65, 131071, 0),        # 2*64*131071 = 2^24 - 128: fp32 pipe
+    (65, 131072, 0),        # 2^24: uint32
+    (300, 1 << 21, 0),      # far above the bound
+    (200, 1000, 1 << 29),   # huge diagonal entries are not weights
+    (150, 1 << 29, 0),      # sums reach 2^30: saturation
+    (1000, 1000, 0),        # lookahead, fp32 pipe
+    (2100, 3, 0),           # 17 rounds
+])
+def test_int32_fp32_pipe_bound_single(apsp, dev, n, whi, diag):
+    """apsp_solve takes the fp32 pipe for int32 only when exact: results equal
+    the oracle bit for bit on both sides of 2 (n-1) wmax < 2^24."""
+    rng = gg.rng_for(gg.CFG_TEST, 1400 + n + whi)
+    W = rng.integers(max(1, whi // 2), whi + 1, size=(n, n), dtype=np.int64)
+    W[rng.random((n, n)) > min(1.0, 6.0 / n)] = INF
+    np.fill_diagonal(W, diag)
+    W = W.astype(np.int32)
+    assert np.array_equal(_solve(apsp, W, dev).astype(np.int64), oracle.fw(W, threads=4))
+
+
+def test_int32_slices_switch_pipes(apsp, dev):
+    """A solve split in round slices rescans each slice's starting matrix: the
+    input qualifies for the fp32 pipe, later states (larger lengths) may not;
+    the result is exact either way."""
+    import torch
+
+    n = 700
+    rng = gg.rng_for(gg.CFG_TEST, 1500)
+    W = rng.integers(1, 1 << 13, size=(n, n), dtype=np.int64)
+    W[rng.random((n, n)) > 4.0 / n] = INF
+    W = W.astype(np.int32)
+    assert 2 * (n - 1) * int(W[W < INF].max()) < (1 << 24)
+    view, _ = _to_dev(W, dev)
+    q = apsp.num_rounds(n)
+    for r0 in range(q):
+        apsp.solve_rounds(view, r0, r0 + 1)
+        torch.cuda.synchronize()
+        part = view.cpu().numpy()
+        if r0 + 1 < q:
+            ref = np.minimum(oracle.fw_steps(oracle.prepare(W), 0, (r0 + 1) * 128, threads=4),
+                             INF)
+            assert np.array_equal(part.astype(np.int64), ref), r0
+    fin = part[part < INF]
+    print(f"final largest length {fin.max()}, bound {2 * (n - 1) * int(fin.max())} vs 2^24")
+    assert np.array_equal(part.astype(np.int64), oracle.fw(W, threads=4))
+
+
 # --------------------------------------------------------------- batched
 
 def _batched_case_sizes():

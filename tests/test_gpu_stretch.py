@@ -19,24 +19,6 @@ ROUNDS = 3
 REL_TOL = 1e-5
 
 
-def _with_hubs(u, v, w, K, seed):
-    """The kNN edges plus a star from vertex 0 to vertices 1..K-1 and an edge
-    from every other vertex j to vertex j % K, so that after the first K
-    pivots most entries are finite (a kNN graph alone leaves nearly all of
-    them "no edge") through paths of a few hops."""
-    rng = gg.rng_for(gg.CFG_TEST, seed)
-    j = np.arange(K, N, dtype=np.int64)
-    hu = np.concatenate([np.zeros(K - 1, dtype=np.int64), j])
-    hv = np.concatenate([np.arange(1, K, dtype=np.int64), j % K])
-    hw = rng.uniform(0.5, 1.5, size=hu.size).astype(np.float32)
-    u, v = np.asarray(u, np.int64), np.asarray(v, np.int64)
-    key = np.minimum(u, v) * N + np.maximum(u, v)
-    hkey = np.minimum(hu, hv) * N + np.maximum(hu, hv)
-    keep = ~np.isin(hkey, key)  # no parallel edges
-    return (np.concatenate([u, hu[keep]]), np.concatenate([v, hv[keep]]),
-            np.concatenate([np.asarray(w, np.float32), hw[keep]]))
-
-
 @pytest.mark.parametrize("hubs", [False, True])
 def test_stretch_262144_first_rounds(hubs):
     import torch
@@ -51,7 +33,8 @@ def test_stretch_262144_first_rounds(hubs):
 
     u, v, w = gg.swiss_roll_knn(N, gg.CFG_SWISS_256K, 0)
     if hubs:
-        u, v, w = _with_hubs(u, v, w, ROUNDS * apsp.round_width(N), 7)
+        u, v, w = gg.with_hub_edges(N, u, v, w, ROUNDS * apsp.round_width(N),
+                                    gg.rng_for(gg.CFG_TEST, 7))
     D = gg.device_dense_from_edges(N, u, v, w, np.float32, "cuda:0")
     apsp.solve_rounds(D, 0, ROUNDS)
     torch.cuda.synchronize()
