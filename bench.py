@@ -388,7 +388,26 @@ def bench_variants(apsp, torch, dev, pristine, work, n: int, b: int) -> dict:
     out["int32_solve"] = {"n": n, "weights": "U{1..100} dense", "ms": round(t_int * 1e3, 3),
                           "T_cell_updates_per_s": round(float(n) ** 3 / t_int / 1e12, 3)}
     log(f"variants: int32 solve n={n} {t_int * 1e3:.1f} ms")
+    # The same fp32 kernels on other data: the GPU is power-limited and the
+    # power depends on how many bits the operands toggle.
+    Pf = Pi.float()
     del Pi, Xi
+    Xf = torch.empty_like(Pf)
+
+    def f32_solve():
+        Xf.copy_(Pf)
+        apsp.solve(Xf)
+
+    t_fint = timed(f32_solve)
+    Pf.uniform_(0.5, 1.5, generator=g2)
+    t_frand = timed(f32_solve)
+    out["data_sensitivity"] = {
+        "n": n, "swiss_roll_ms": round(t_full * 1e3, 3),
+        "f32_integer_valued_U1_100_ms": round(t_fint * 1e3, 3),
+        "f32_uniform_0.5_1.5_ms": round(t_frand * 1e3, 3)}
+    log(f"variants: fp32 solve n={n}: integer-valued weights {t_fint * 1e3:.1f} ms, "
+        f"uniform [0.5, 1.5) {t_frand * 1e3:.1f} ms, Swiss roll {t_full * 1e3:.1f} ms")
+    del Pf, Xf
     return out
 
 
