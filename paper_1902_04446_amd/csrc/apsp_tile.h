@@ -325,112 +325,72 @@ __device__ __forceinline__ void minplus_tile(uint32_t (&acc)[8][8], const uint32
 // ---------------------------------------------------------------------------
 // Floyd-Warshall closure of a (kw x kw, kw <= 128) diagonal block held in
 // registers in the layout above (thread (tx, ty) holds rows
-// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).
+// {ty*4 + m, 64 + ty*4 + m}, columns {tx*4 + e, 64 + tx*4 + e}).  Pivot k:
+// the 16 threads holding row k and the 16 holding column k publish them to
+// LDS (double-buffered, one barrier per pivot), then every thread applies
+// d_ij = min(d_ij, d_ik + d_kj) to its entries.  Same operations in the same
+// order as the textbook loop, so the same bits.  A block of kw <= 64
+// vertices lives in acc rows m < 4, columns e < 4, and only that quadrant is
+// updated.  `lds` needs 4 x 128 words; every thread returns after the last
+// pivot's barrier.
 //
-// Pivots go in ascending pairs (k, k+1), one barrier per pair: the owners of
-// rows k, k+1 and columns k, k+1 publish them to LDS (double-buffered) as
-// they stand before pivot k.  Every thread then forms what pivot k does to
-// row and column k+1 on its own columns / rows,
-//     r1'[j] = min(r1[j], d[k+1][k] + r0[j]),  c1'[i] = min(c1[i], c0[i] + d[k][k+1]),
-// and applies both pivots with one min3:
-//     d[i][j] = min3(d[i][j], c0[i] + r0[j], c1'[i] + r1'[j]).
-// These are the textbook loop's sums (pivot row and column k do not change
-// under pivot k, as d[k][k] = 0) and the minimum is exact, so the bits are
-// those of the sequential loop.  A block of kw <= 64 vertices updates only
-// the quadrant that holds it.  `lds` needs 8 x 128 words; every thread
-// returns after the last pair's barrier.
+// (Applying pivots in pairs, one barrier per pair and one min3 per entry,
+// does fewer instructions but lengthens each barrier-to-barrier step; it
+// measured slower on the rounds' critical chain.)
 // ---------------------------------------------------------------------------
 template <class Op>
 __device__ __forceinline__ void close_block(uint32_t (&acc)[8][8], int kw, uint32_t *lds) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    // a block of at most 64 vertices lives in acc rows m < 4, columns e < 4
     const bool big = kw > 64;
-    // rowbuf(sel, v) = lds + sel*256 + v*128, colbuf(sel, v) = lds + 512 + sel*256 + v*128
+    uint32_t *rowbuf = lds;            // [2][128]
+    uint32_t *colbuf = lds + 2 * TB;   // [2][128]
+    // pivots in ascending order: k = kh*64 + kq*4 + u
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh) {
         for (int kq = 0; kq < 16; ++kq) {
 #pragma unroll
-            for (int up = 0; up < 2; ++up) {
-                const int k = kh * 64 + kq * 4 + up * 2;  // first pivot of the pair
-                if (k < kw) {                             // kw is uniform
-                    const int sel = (k >> 1) & 1;
-                    const int mk = kh * 4 + up * 2;  // register row/column index of pivot k
-                    uint32_t *rb = lds + sel * 256;
-                    uint32_t *cb = lds + 512 + sel * 256;
+            for (int u = 0; u < 4; ++u) {
+                const int k = kh * 64 + kq * 4 + u;
+                if (k < kw) {
+                    const int sel = (k & 1) * TB;
+                    const int mk = kh * 4 + u;  // register row/column index of pivot k
                     if (ty == kq) {
 #pragma unroll
-                        for (int v = 0; v < 2; ++v)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-                                *reinterpret_cast<uint4 *>(&rb[v * 128 + h * 64 + tx * 4]) =
-                                    make_uint4(acc[mk + v][h * 4 + 0], acc[mk + v][h * 4 + 1],
-                                               acc[mk + v][h * 4 + 2], acc[mk + v][h * 4 + 3]);
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&rowbuf[sel + h * 64 + tx * 4]) =
+                                make_uint4(acc[mk][h * 4 + 0], acc[mk][h * 4 + 1],
+                                           acc[mk][h * 4 + 2], acc[mk][h * 4 + 3]);
                     }
                     if (tx == kq) {
 #pragma unroll
-                        for (int v = 0; v < 2; ++v)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-                                *reinterpret_cast<uint4 *>(&cb[v * 128 + h * 64 + ty * 4]) =
-                                    make_uint4(acc[h * 4 + 0][mk + v], acc[h * 4 + 1][mk + v],
-                                               acc[h * 4 + 2][mk + v], acc[h * 4 + 3][mk + v]);
+                        for (int h = 0; h < 2; ++h)
+                            *reinterpret_cast<uint4 *>(&colbuf[sel + h * 64 + ty * 4]) =
+                                make_uint4(acc[h * 4 + 0][mk], acc[h * 4 + 1][mk],
+                                           acc[h * 4 + 2][mk], acc[h * 4 + 3][mk]);
                     }
                     __syncthreads();
-                    uint32_t c0[8], c1[8];
+                    uint32_t dik[8], dkj[8];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const uint4 c = *reinterpret_cast<const uint4 *>(&cb[h * 64 + ty * 4]);
-                        const uint4 d = *reinterpret_cast<const uint4 *>(&cb[128 + h * 64 + ty * 4]);
-                        c0[h * 4 + 0] = c.x; c0[h * 4 + 1] = c.y; c0[h * 4 + 2] = c.z; c0[h * 4 + 3] = c.w;
-                        c1[h * 4 + 0] = d.x; c1[h * 4 + 1] = d.y; c1[h * 4 + 2] = d.z; c1[h * 4 + 3] = d.w;
+                        const uint4 c4 = *reinterpret_cast<const uint4 *>(&colbuf[sel + h * 64 + ty * 4]);
+                        const uint4 r4 = *reinterpret_cast<const uint4 *>(&rowbuf[sel + h * 64 + tx * 4]);
+                        dik[h * 4 + 0] = c4.x; dik[h * 4 + 1] = c4.y;
+                        dik[h * 4 + 2] = c4.z; dik[h * 4 + 3] = c4.w;
+                        dkj[h * 4 + 0] = r4.x; dkj[h * 4 + 1] = r4.y;
+                        dkj[h * 4 + 2] = r4.z; dkj[h * 4 + 3] = r4.w;
                     }
-                    if (k + 1 < kw) {
-                        const uint32_t x01 = rb[k + 1];    // d[k][k+1]
-                        const uint32_t x10 = rb[128 + k];  // d[k+1][k]
 #pragma unroll
-                        for (int m = 0; m < 8; ++m) c1[m] = Op::min2(c1[m], Op::add(c0[m], x01));
-                        // one half of the columns at a time keeps fewer values live
+                    for (int m = 0; m < 4; ++m)
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            if (h == 1 && !big) break;
-                            const uint4 a = *reinterpret_cast<const uint4 *>(&rb[h * 64 + tx * 4]);
-                            const uint4 b = *reinterpret_cast<const uint4 *>(&rb[128 + h * 64 + tx * 4]);
-                            const uint32_t r0[4] = {a.x, a.y, a.z, a.w};
-                            uint32_t r1[4] = {b.x, b.y, b.z, b.w};
+                        for (int e = 0; e < 4; ++e)
+                            acc[m][e] = Op::min2(acc[m][e], Op::add(dik[m], dkj[e]));
+                    if (big) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) r1[e] = Op::min2(r1[e], Op::add(x10, r0[e]));
+                        for (int m = 0; m < 8; ++m)
 #pragma unroll
-                            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    acc[m][h * 4 + e] = Op::min3(acc[m][h * 4 + e], Op::add(c0[m], r0[e]),
-                                                                 Op::add(c1[m], r1[e]));
-                            if (big) {
-#pragma unroll
-                                for (int m = 4; m < 8; ++m)
-#pragma unroll
-                                    for (int e = 0; e < 4; ++e)
-                                        acc[m][h * 4 + e] =
-                                            Op::min3(acc[m][h * 4 + e], Op::add(c0[m], r0[e]),
-                                                     Op::add(c1[m], r1[e]));
-                            }
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    } else {  // odd kw: the last pivot alone
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            if (h == 1 && !big) break;
-                            const uint4 a = *reinterpret_cast<const uint4 *>(&rb[h * 64 + tx * 4]);
-                            const uint32_t r0[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-                            for (int m = 0; m < 8; ++m) {
-                                if (m >= 4 && !big) break;
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    acc[m][h * 4 + e] =
-                                        Op::min2(acc[m][h * 4 + e], Op::add(c0[m], r0[e]));
-                            }
-                        }
+                            for (int e = 0; e < 8; ++e)
+                                if (m >= 4 || e >= 4)
+                                    acc[m][e] = Op::min2(acc[m][e], Op::add(dik[m], dkj[e]));
                     }
                 }
             }
