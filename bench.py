@@ -489,8 +489,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the whole matrix lives in one MI355X's HBM and this "
-              "build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the whole matrix lives in one MI355X's HBM and the "
+              "library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -54,7 +54,7 @@ enum { APSP_I32 = 0, APSP_F32 = 1 };
 enum {
     APSP_OK = 0,
     APSP_ERR_INVALID_VALUE = 1, /* bad size, leading dimension, pointer, dtype or count */
-    APSP_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve */
+    APSP_ERR_UNSUPPORTED = 2,   /* valid request this library version cannot serve */
     APSP_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
     APSP_ERR_NO_MEMORY = 4,     /* device workspace could not be allocated */
     APSP_ERR_BAD_INPUT = 5      /* apsp_validate(): negative weight or NaN found */

@@ -197,7 +197,7 @@ const char *apsp_status_string(int32_t status) {
     switch (status) {
     case APSP_OK: return "APSP_OK";
     case APSP_ERR_INVALID_VALUE: return "APSP_ERR_INVALID_VALUE: bad size, leading dimension, pointer, dtype or count";
-    case APSP_ERR_UNSUPPORTED: return "APSP_ERR_UNSUPPORTED: request not supported by this build";
+    case APSP_ERR_UNSUPPORTED: return "APSP_ERR_UNSUPPORTED: request not supported by this library version";
     case APSP_ERR_DEVICE: return "APSP_ERR_DEVICE: a HIP call or kernel launch failed";
     case APSP_ERR_NO_MEMORY: return "APSP_ERR_NO_MEMORY: device workspace allocation failed";
     case APSP_ERR_BAD_INPUT: return "APSP_ERR_BAD_INPUT: negative weight or NaN in the matrix";

@@ -327,7 +327,7 @@ class ApspServer:
                 req.next_round = r1
                 progressed = True
 
-    # -------------------------------------------------------------- driver
+    # ------------------------------------------------------------ run loop
     def run(self, requests, realtime: bool = True, spin: float = 2e-5) -> dict:
         """Serve a whole request stream (arrival times relative to the start)."""
         reqs = sorted(requests, key=lambda r: r.arrival)

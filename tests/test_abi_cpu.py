@@ -277,3 +277,12 @@ def test_phase_tile_maps_are_bijections(q):
                     assert all(lo <= i < hi for i, _ in band)
                     got += band
                 assert len(got) == len(set(got)) and set(got) == set(rest)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asked for more it says so and exits 2 before
+    touching any device."""
+    out = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr and out.stdout == ""
