@@ -525,8 +525,11 @@ def main() -> int:
     phases = {"prologue": 0.0, "phase1": 0.0, "phase2": 0.0, "phase3": 0.0, "total": 0.0,
               "phase3_rest": 0.0, "phase3_rest_launches": 0.0, "phase3_other": 0.0}
     t0 = time.perf_counter()
+    step_ms = []
     for i in range(args.steps):
-        t = step()
+        ts = time.perf_counter()
+        t = step()  # the profiled solve waits for its own completion
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         for key in phases:
             phases[key] += t[key]
         log(f"step {i}: solve {t['total']:.1f} ms (phase3 {t['phase3']:.1f} ms)")
@@ -603,6 +606,8 @@ def main() -> int:
                                "fp32 dense matrix, +inf non-edges",
                    "n": n, "round_width": b, "rounds": q},
         "phase_ms": phase_ms,
+        "step_ms": {"min": round(min(step_ms), 3),
+                    "median": round(sorted(step_ms)[len(step_ms) // 2], 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "valu_probe": probe,
