@@ -33,16 +33,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # VALU ceiling of MI355X for the min-plus update, from unit counts and clock:
-# 256 CUs at 2.4 GHz.  fp32/int32 adds issue at 128 lanes/clk/CU (the 157.3
-# TFLOP/s fp32 vector figure is 256 x 128 x 2 flops x 2.4e9); min/max-class
-# instructions (v_min3_i32, v_min3_u32) issue at half that, 64 lanes/clk/CU
-# (measured by the VALU probe below).  Two updates with k-paired candidates
-# cost 2 adds + 1 three-input min: 2/128 + 1/64 = 2/64 CU-clock-lanes, so
-# 64 updates per clock per CU.
+# 256 CUs at 2.4 GHz issue 128 fp32 lanes per clock each (the 157.3 TFLOP/s
+# fp32 vector figure is 256 x 128 lanes x 2 flops x 2.4e9).  The update costs
+# 1.5 VALU instructions (2 adds + 1 three-input min per 2 updates); at one
+# lane-instruction per lane-slot that is 128 / 1.5 updates per clock per CU.
+# (v_min3 alone issues at half the add rate, but interleaved with the adds the
+# mix gets close to this bound: the probe's update_mix figure.)
 CUS, CLOCK_HZ = 256, 2.4e9
-ADD_LANES_PER_CLK, MIN_LANES_PER_CLK = 128, 64
-UPDATES_PER_CLK_PER_CU = 1.0 / (1.0 / ADD_LANES_PER_CLK + 0.5 / MIN_LANES_PER_CLK)
-VALU_PEAK_UPD = CUS * CLOCK_HZ * UPDATES_PER_CLK_PER_CU   # 39.32e12 updates/s
+LANES_PER_CLK = 128
+VALU_INSTR_PER_UPDATE = 1.5
+UPDATES_PER_CLK_PER_CU = LANES_PER_CLK / VALU_INSTR_PER_UPDATE
+VALU_PEAK_UPD = CUS * CLOCK_HZ * UPDATES_PER_CLK_PER_CU   # 52.43e12 updates/s
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
@@ -88,10 +89,13 @@ def valu_probe() -> dict | None:
         return None
     add_f32, add_u32, min3_i32, min3_u32 = (float(x) for x in rates)
     ceiling = 1.0 / (1.0 / add_f32 + 0.5 / min3_i32)
+    mix = ctypes.c_double(0.0)
+    mix_t = mix.value / 1e12 if lib.apsp_probe_update_mix(ctypes.byref(mix)) == 0 else None
     return {"unit": "T lane-instr/s", "v_add_f32": round(add_f32 / 1e12, 2),
             "v_add_u32": round(add_u32 / 1e12, 2), "v_min3_i32": round(min3_i32 / 1e12, 2),
             "v_min3_u32": round(min3_u32 / 1e12, 2),
-            "measured_update_ceiling_T": round(ceiling / 1e12, 2)}
+            "standalone_rates_in_sequence_T": round(ceiling / 1e12, 2),
+            "update_mix_T_updates_per_s": round(mix.value / 1e12, 2) if mix_t else None}
 
 
 def phase3_traffic() -> float | None:
