@@ -472,6 +472,67 @@ def bench_stretch(apsp, torch, dev, rounds: int) -> dict:
             "projected_T_cell_updates_per_s": round(float(n) ** 3 / projected / 1e12, 3)}
 
 
+def rest_roofline(phases: dict, K: int, n: int, b: int) -> dict:
+    """Roofline entry of the dominant phase-3 kernel from K profiled solves
+    (summed phase times in ms)."""
+    q = -(-n // b)
+    rest_upd, rest_launches = phase3_rest_updates(n, b)
+    launches = phases["phase3_rest_launches"] / K
+    if q >= 3 and launches == rest_launches:
+        kernel = ("k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles; two "
+                  "concurrent launches per round, one per band of block rows; per-launch "
+                  "figures are per round)")
+        launch_s = phases["phase3_rest"] / K / 1e3 / rest_launches
+        per_launch = rest_upd / rest_launches
+    else:  # no lookahead split at this size: whole phase 3 in one launch per round
+        kernel = "k_tiles<kAll> (phase 3, 128x128 tiles)"
+        launch_s = phases["phase3"] / K / 1e3 / q
+        per_launch = sum((n - min(b, n - r * b)) ** 2 * min(b, n - r * b) for r in range(q)) / q
+    achieved = per_launch / launch_s
+    return {
+        "bound": "alu",
+        "kernel": kernel,
+        "achieved": round(achieved / 1e12, 3),
+        "peak": round(VALU_PEAK_UPD / 1e12, 3),
+        "unit": "T cell-updates/s",
+        "frac": round(achieved / VALU_PEAK_UPD, 4),
+        "traffic": None,
+        "per_launch_updates": round(per_launch),
+        "avg_launch_ms": round(launch_s * 1e3, 4),
+    }
+
+
+def bench_long(apsp, torch, dev, n: int = 65536) -> dict:
+    """One full solve of the n = 65536 Swiss-roll kNN workload (16 GiB fp32
+    matrix, 512 rounds): whole-solve throughput and per-phase times."""
+    import numpy as np
+
+    import graphgen as gg
+
+    need = n * n * 4
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (2 << 30):
+        return {"n": n, "skipped": f"{free / 2**30:.0f} GiB of device memory free"}
+    log(f"long run: building Swiss-roll kNN graph n={n} (16 GiB matrix)")
+    u, v, w = gg.swiss_roll_knn(n, gg.CFG_SWISS_64K, 0)
+    D = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+    del u, v, w
+    torch.cuda.synchronize()
+    b = apsp.round_width(n, apsp.APSP_F32)
+    t0 = time.perf_counter()
+    t = apsp.solve_profiled(D)
+    wall = time.perf_counter() - t0
+    del D
+    torch.cuda.empty_cache()
+    log(f"long run: n={n} solve {t['total']:.0f} ms ({wall:.2f} s wall)")
+    return {"n": n, "matrix_GiB": need / 2**30, "round_width": b, "rounds": -(-n // b),
+            "workload": "Swiss-roll kNN (k=10, union), fp32",
+            "solve_ms": round(t["total"], 1), "wall_s": round(wall, 3),
+            "T_cell_updates_per_s": round(float(n) ** 3 / (t["total"] * 1e-3) / 1e12, 3),
+            "phase_ms": {k: round(vv, 3) for k, vv in t.items()},
+            "roofline": rest_roofline(t, 1, n, b)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,6 +549,8 @@ def main() -> int:
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
     ap.add_argument("--batched-loop", type=int, default=1,
                     help="also time the batch as a loop of single-graph solves (0 skips it)")
+    ap.add_argument("--long-run", type=int, default=1,
+                    help="one full n=65536 solve with per-phase times (0 disables it)")
     ap.add_argument("--stretch-rounds", type=int, default=3,
                     help="timed rounds of the n=262144 solve (0 disables it)")
     args = ap.parse_args()
@@ -506,7 +569,8 @@ def main() -> int:
     n = args.n
     dev = torch.device("cuda:0")
     log(f"building Swiss-roll kNN graph n={n}")
-    u, v, w = gg.swiss_roll_knn(n, gg.CFG_SWISS_16K if n == 16384 else gg.CFG_TEST, 0)
+    cfg = {16384: gg.CFG_SWISS_16K, 65536: gg.CFG_SWISS_64K}.get(n, gg.CFG_TEST)
+    u, v, w = gg.swiss_roll_knn(n, cfg, 0)
     pristine = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
     work = torch.empty_like(pristine)
     # a plain elementwise read+write of the matrix: the calibration kernel for
@@ -544,31 +608,8 @@ def main() -> int:
     phase_ms = {k: round(vv / K, 3) for k, vv in phases.items()}
 
     q = -(-n // b)
-    rest_upd, rest_launches = phase3_rest_updates(n, b)
-    launches = phases["phase3_rest_launches"] / K
-    if q >= 3 and launches == rest_launches:
-        kernel = ("k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles; two "
-                  "concurrent launches per round, one per band of block rows; per-launch "
-                  "figures are per round)")
-        launch_s = phases["phase3_rest"] / K / 1e3 / rest_launches
-        per_launch = rest_upd / rest_launches
-    else:  # no lookahead split at this size: whole phase 3 in one launch per round
-        kernel = "k_tiles<kAll> (phase 3, 128x128 tiles)"
-        launch_s = phases["phase3"] / K / 1e3 / q
-        per_launch = sum((n - min(b, n - r * b)) ** 2 * min(b, n - r * b) for r in range(q)) / q
-    achieved = per_launch / launch_s
-    traffic = phase3_traffic()
-    roofline = {
-        "bound": "alu",
-        "kernel": kernel,
-        "achieved": round(achieved / 1e12, 3),
-        "peak": round(VALU_PEAK_UPD / 1e12, 3),
-        "unit": "T cell-updates/s",
-        "frac": round(achieved / VALU_PEAK_UPD, 4),
-        "traffic": traffic,
-        "per_launch_updates": round(per_launch),
-        "avg_launch_ms": round(launch_s * 1e3, 4),
-    }
+    roofline = rest_roofline(phases, K, n, b)
+    roofline["traffic"] = phase3_traffic() if n == 16384 else None
 
     variants = None
     if args.variants:
@@ -583,6 +624,13 @@ def main() -> int:
     if args.serving > 0:
         serving = bench_serving(apsp, torch, dev, args.serving)
 
+    long_run = None
+    if args.long_run > 0 and n != 65536:
+        del pristine, work
+        torch.cuda.empty_cache()
+        pristine = work = None
+        long_run = bench_long(apsp, torch, dev)
+
     stretch = None
     if args.stretch_rounds > 0:
         del pristine, work
@@ -594,7 +642,7 @@ def main() -> int:
         cpu = cpu_baseline(n, u, v, w, args.cpu_seconds)
 
     out = {
-        "metric": "APSP cell-updates/s (n^3/t), n=16384 FP32",
+        "metric": f"APSP cell-updates/s (n^3/t), n={n} FP32",
         "value": round(value / 1e12, 4),
         "unit": "T cell-updates/s",
         "n_gpus": 1,
@@ -618,6 +666,7 @@ def main() -> int:
         "variants": variants,
         "batched": batched,
         "serving": serving,
+        "long_run": long_run,
         "stretch": stretch,
     }
     print(json.dumps(out), flush=True)
