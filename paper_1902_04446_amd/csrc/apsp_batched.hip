@@ -91,9 +91,11 @@ __device__ __forceinline__ void any_item(const BatchDesc &g, bool vec, int I, in
 // One work item per workgroup: a tile of round r of one graph, at that
 // graph's round width (g.tile, 64 or 128).  DT 0: int32 graphs, each on the
 // fp32 pipe (OpI32F) when its largest finite weight wmax[graph] allows it
-// bit-exactly, else in uint32; DT 1: fp32.
+// bit-exactly, else in uint32; DT 1: fp32.  A closure-only launch (phase 1
+// of the first round) is bound by its serial pivot chains, so it is built
+// for 4 workgroups per CU rather than 3: more closures overlap per CU.
 template <int DT, bool CLOSE_ONLY>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_batched(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CLOSE_ONLY ? 4 : 3))) void k_batched(
     const BatchDesc *__restrict__ descs, const BatchItem *__restrict__ items, XcdRanges ranges,
     int r, const uint32_t *__restrict__ wmax) {
     constexpr size_t kLds =
