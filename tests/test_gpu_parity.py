@@ -333,6 +333,32 @@ def test_int32_slices_switch_pipes(apsp, dev):
     assert np.array_equal(part.astype(np.int64), oracle.fw(W, threads=4))
 
 
+@pytest.mark.parametrize("whi", [100, 1 << 20])
+def test_banded_ragged_int32_rows(apsp, dev, whi):
+    """n = 8300: 65 rounds, so phase 3 runs as two bands of block rows with the
+    one-round lookahead, and the last block is partial (8300 = 64 * 128 + 108).
+    U{1..100} takes the fp32 pipe, U{1..2^20} uint32.  Sampled rows and
+    columns (the last vertex among them) equal the oracle's Dijkstra exactly,
+    and the exact Bellman certificate holds on a larger sample of rows."""
+    import torch
+
+    n = 8300
+    rng = gg.rng_for(gg.CFG_TEST, 1600 + whi)
+    u, v, w = gg.er_edges(n, 6.0 / n, 1, whi, rng)
+    D = gg.device_dense_from_edges(n, u, v, w, np.int32, dev)
+    assert apsp.num_rounds(n) == 65
+    apsp.solve(D)
+    torch.cuda.synchronize()
+    csr = gg.csr_from_edges(n, u, v, w)
+    src = np.unique(np.concatenate([rng.choice(n, size=23, replace=False), [n - 1]]))
+    ref = oracle.dijkstra(csr, n, src, threads=16, integer=True)
+    tsrc = torch.as_tensor(src, device=dev)
+    assert np.array_equal(D[tsrc].cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(D[:, tsrc].cpu().numpy().T.astype(np.int64), ref)
+    brows = rng.choice(n, size=1500, replace=False)
+    assert oracle.bellman_violations_i32(D.cpu().numpy(), csr, brows, threads=16) == 0
+
+
 # --------------------------------------------------------------- batched
 
 def _batched_case_sizes():
