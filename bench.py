@@ -50,7 +50,7 @@ TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
 # the phase-3 kernel and the schedule that launches it (the traffic figures
 # hold while these sources are unchanged)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_04446_amd", "csrc", f)
-                  for f in ("apsp_plain.hip", "apsp_tile.h", "apsp_runtime.hip")]
+                  for f in ("apsp_plain.hip", "apsp_pair.hip", "apsp_tile.h", "apsp_runtime.hip")]
 
 
 def cell_updates_per_s(n: int, seconds: float) -> float:
@@ -74,6 +74,32 @@ def phase3_rest_updates(n: int, b: int) -> tuple[int, int]:
         kw1 = min(b, n - (r + 1) * b)
         total += (n - kw - kw1) ** 2 * kw
     return total, q - 1
+
+
+def phase3_pair_updates(n: int, b: int) -> tuple[int, int]:
+    """The same for the round-pair schedule: one rest launch group per pair of
+    rounds (r, r+1), over the entries outside block rows/columns r .. r+3, each
+    with |K_r| + |K_r+1| candidates, plus round r-1's deferred update of the
+    previous pair's block row/column r-2 that those launches apply; and the
+    number of pairs.  With an odd round count the last round runs alone."""
+    q = -(-n // b)
+
+    def w(x):
+        return min(b, n - x * b) if 0 <= x < q else 0
+
+    total, pairs = 0, 0
+    r = 0
+    while r + 1 < q:
+        excl = sum(w(x) for x in range(r, min(r + 4, q)))
+        out = n - excl
+        total += out * out * (w(r) + w(r + 1))
+        if r >= 2:
+            p = r - 2
+            side = out - w(p + 1)
+            total += (2 * w(p) * side - w(p) * w(p)) * w(p + 1)
+        pairs += 1
+        r += 2
+    return total, pairs
 
 
 def valu_probe() -> dict | None:
@@ -477,8 +503,16 @@ def rest_roofline(phases: dict, K: int, n: int, b: int) -> dict:
     (summed phase times in ms)."""
     q = -(-n // b)
     rest_upd, rest_launches = phase3_rest_updates(n, b)
+    pair_upd, pair_launches = phase3_pair_updates(n, b)
     launches = phases["phase3_rest_launches"] / K
-    if q >= 3 and launches == rest_launches:
+    if q >= 3 and launches == pair_launches:
+        kernel = ("k_pair<kRest2> (phase 3 of a pair of rounds in one pass, k over two "
+                  "blocks, outside block rows/columns r .. r+3; 128x128 tiles; two concurrent "
+                  "launches per pair, one per band of block rows; per-launch figures are per "
+                  "pair of rounds)")
+        launch_s = phases["phase3_rest"] / K / 1e3 / pair_launches
+        per_launch = pair_upd / pair_launches
+    elif q >= 3 and launches == rest_launches:
         kernel = ("k_tiles<kRest> (phase 3 minus block row/column r+1, 128x128 tiles; two "
                   "concurrent launches per round, one per band of block rows; per-launch "
                   "figures are per round)")

@@ -141,6 +141,41 @@ hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
                             int64_t hi, hipStream_t s, const uint32_t *wmax = nullptr);
 int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 int64_t num_rounds(int64_t n);
+
+// ---- round pairs (apsp_pair.hip) -------------------------------------------
+// Copies of round pr's block row and block column, written by phase 2 of the
+// second round of a pair; three slots.  row[s]: 128 x ld (row k of the block
+// row at offset k*ld); col[s]: q*128 x 128 (the block column's row i at
+// offset i*128).
+struct PairCopies {
+    uint32_t *row[3] = {};
+    uint32_t *col[3] = {};
+    int64_t ld = 0;
+};
+// Blocks r+2, r+3 that exist (0..2): the next pair's.
+int pair_next_blocks(int64_t n, int64_t r);
+// Phase 2 of round pr, also written to copy slot `slot`.
+hipError_t launch_pair_panels(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t pr,
+                              const PairCopies &c, int slot, hipStream_t s,
+                              const uint32_t *wmax);
+// Phase 3 of rounds r and r+1 on the tiles of block rows/columns r+2, r+3
+// outside blocks r, r+1; `close` closes diagonal block r+2 after its update.
+// prev >= 0: tiles of block row/column prev (but prev+1) first take round
+// prev+1's deferred update from copy slot prev_slot.
+hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                            bool close, int64_t prev, const PairCopies &c, int prev_slot,
+                            hipStream_t s, const uint32_t *wmax);
+// Phase 3 of rounds r and r+1 on the tiles outside blocks r .. r+1+next
+// whose block row is in [lo, hi); deferred updates as launch_pair_next.
+hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                            int64_t lo, int64_t hi, int64_t prev, const PairCopies &c,
+                            int prev_slot, hipStream_t s, const uint32_t *wmax);
+int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
+// Round r+1's deferred phase-3 update on block row/column r: !final_: tiles
+// (x, r), (r, x) for the next blocks x; final_: every other one but the
+// blocks r+1.
+hipError_t launch_pair_fix(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, bool final_,
+                           hipStream_t s, const uint32_t *wmax);
 int64_t tile_count(int64_t n, int64_t r, int set);
 hipError_t launch_validate(const uint32_t *D, int64_t n, int64_t ld, int dtype, uint32_t *flag,
                            hipStream_t s);

@@ -1,0 +1,292 @@
+// Round pairs for the single-graph solver: phase 3 of rounds r and r+1 in one
+// pass over each tile (arXiv:1902.04446, Sec. 4.4/4.5: the three phases of
+// Algorithms 3 and 4, applied to two consecutive rounds).
+//
+// For a tile (I, J) outside block rows/columns r and r+1, the two rounds'
+// phase-3 updates are
+//     D'  = min(D,  D'[I,r] (x) D'[r,J])                 round r
+//     D'' = min(D', D''[I,r+1] (x) D''[r+1,J])           round r+1
+// where D'[., r] / D'[r, .] are round r's panels (after its phase 2) and
+// D''[., r+1] / D''[r+1, .] round r+1's.  Since min is exact and every
+// candidate is one addition, D'' = min(D, both products): one pass with k
+// over blocks r and r+1 (256 wide) gives the same bits, reading and writing
+// the tile once instead of twice.  That needs block column r and block row r
+// to hold round r's panels during the pass, so round r+1's phase 3 on those
+// tiles (their "pending" update) is deferred:
+//   * tiles (x, r), (r, x) for the next pair's blocks x = r+2, r+3 get it
+//     right after the next pair's first tiles are done (kFix, next);
+//   * the other tiles of block row/column r get it at the start of their
+//     update in the next pair's pass, from a copy of round r+1's panels
+//     taken when phase 2 of round r+1 wrote them (by then the next pair may
+//     have changed block row/column r+1 in the matrix itself);
+//   * at the end of a call, kFix (final) applies what is left, so a call
+//     always leaves exactly the state of Floyd-Warshall after its last round.
+// The schedule (apsp_runtime.hip) keeps every read of these tiles ahead of
+// every write to them; the result is the same as running the rounds one by
+// one, bit for bit.
+#include <algorithm>
+
+#include "apsp_tile.h"
+
+namespace apsp {
+
+namespace {
+
+using tile::NT;
+using tile::TB;
+
+// Tile sets of the pair launches.
+constexpr int kPanelsSnap = 0;  // phase 2 of round pr, also written to the copy
+constexpr int kNext2 = 1;       // pair pass on block rows/columns r+2, r+3 (outside r, r+1)
+constexpr int kRest2 = 2;       // pair pass on a band of block rows, outside blocks [r, r+2+nxt)
+constexpr int kFix = 3;         // round r+1's deferred update of block row/column r tiles
+
+struct PairArgs {
+    uint32_t *D;
+    int64_t ld, n;
+    int r;       // first round of the pair (kPanelsSnap: the panel round)
+    int q;
+    int vec;     // 16-byte aligned rows of D
+    int nxt;     // next-pair blocks present: r+2, r+3 below q (0..2)
+    int close;   // kNext2: close diagonal block r+2 after its update
+    int lo, hi;  // kRest2: band [lo, hi) of block rows
+    int prev;    // kNext2/kRest2: first round of the previous pair, -1 if none
+    int final_;  // kFix: 0 = tiles (x, r), (r, x) for next blocks x; 1 = the rest
+    const uint32_t *prow;  // copy of the previous pair's round prev+1 block row
+    const uint32_t *pcol;  // ... and block column (rows of 128, leading dimension 128)
+    int64_t ldc;           // leading dimension of the block-row copies
+    uint32_t *srow, *scol; // kPanelsSnap: copies to write (same layout)
+};
+
+__device__ __forceinline__ int width(int64_t n, int blk) {
+    const int64_t w = n - (int64_t)blk * TB;
+    return (int)(w < TB ? w : TB);
+}
+
+// Workgroup -> tile and its update: k blocks [kb, kb + kblocks), deferred
+// update first (pending), closure after (close).
+struct Job {
+    int I, J, kb, kblocks;
+    bool pending, close;
+};
+
+template <int MODE>
+__device__ __forceinline__ Job job_of(const PairArgs &a) {
+    Job j{0, 0, a.r, 2, false, false};
+    const int r = a.r, q = a.q;
+    if (MODE == kPanelsSnap) {
+        // same order as phase 2: block row pr (every column but pr), then
+        // block column pr (every row but pr)
+        int t = blockIdx.x;
+        if (t < q - 1) {
+            j.I = r;
+            j.J = t < r ? t : t + 1;
+        } else {
+            t -= q - 1;
+            j.J = r;
+            j.I = t < r ? t : t + 1;
+        }
+        j.kb = r;
+        j.kblocks = 1;
+        return j;
+    }
+    if (MODE == kFix) {
+        int t = blockIdx.x;
+        if (!a.final_) {  // (x, r) and (r, x), x = r+2 .. r+1+nxt
+            const int x = r + 2 + (t >> 1);
+            j.I = (t & 1) ? r : x;
+            j.J = (t & 1) ? x : r;
+        } else {
+            // block row r but columns r+1 and the next blocks, then block
+            // column r but rows r, r+1 and the next blocks
+            const int rowpart = q - 1 - a.nxt;
+            if (t < rowpart) {
+                j.I = r;
+                j.J = t < r + 1 ? t : t + 1 + a.nxt;
+            } else {
+                t -= rowpart;
+                j.J = r;
+                j.I = t < r ? t : t + 2 + a.nxt;
+            }
+        }
+        j.kb = r + 1;
+        j.kblocks = 1;
+        return j;
+    }
+    const int m = q - 2;  // blocks outside r, r+1
+    if (MODE == kNext2) {
+        // block rows r+2.. (every column outside r, r+1), then block columns
+        // r+2.. (every row outside r .. r+1+nxt)
+        int t = blockIdx.x;
+        if (t < a.nxt * m) {
+            j.I = r + 2 + t / m;
+            const int c = t % m;
+            j.J = c < r ? c : c + 2;
+        } else {
+            t -= a.nxt * m;
+            const int m2 = m - a.nxt;
+            j.J = r + 2 + t / m2;
+            const int c = t % m2;
+            j.I = c < r ? c : c + 2 + a.nxt;
+        }
+        j.close = a.close && j.I == r + 2 && j.J == r + 2;
+    } else {  // kRest2: rows [lo, hi) and columns outside the excluded blocks [r, e1)
+        const int e1 = r + 2 + a.nxt;
+        const int ex = e1 - r;
+        const int x0 = r > a.lo ? r : a.lo, x1 = e1 < a.hi ? e1 : a.hi;
+        const int skipped = x1 > x0 ? x1 - x0 : 0;
+        const int rows = a.hi - a.lo - skipped;
+        const int mc = q - ex;
+        const int T = rows * mc;
+        const int wg = blockIdx.x;
+        const int x = wg & 7, s = wg >> 3;
+        const int per = T >> 3, rem = T & 7;
+        const int tl = x * per + (x < rem ? x : rem) + s;  // one contiguous run per XCD
+        const int ti = tl / mc, tj = tl - ti * mc;
+        j.I = a.lo + ti;
+        if (skipped && j.I >= x0) j.I += skipped;
+        j.J = tj < r ? tj : tj + ex;
+    }
+    j.pending = a.prev >= 0 && (j.I == a.prev || j.J == a.prev) && j.I != a.prev + 1 &&
+                j.J != a.prev + 1;
+    return j;
+}
+
+template <class Op, int MODE, bool NORM>
+__device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
+    const Job jb = job_of<MODE>(a);
+    const int64_t i0 = (int64_t)jb.I * TB, j0 = (int64_t)jb.J * TB;
+    const int mr = width(a.n, jb.I), nc = width(a.n, jb.J);
+    const int64_t kb = (int64_t)jb.kb * TB;
+    const int64_t kwl = a.n - kb;
+    const int kw = (int)(kwl < (int64_t)jb.kblocks * TB ? kwl : (int64_t)jb.kblocks * TB);
+    const bool vec = a.vec != 0;
+
+    uint32_t acc[8][8];
+    tile::load_acc<Op, NORM>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
+    if (MODE != kPanelsSnap && MODE != kFix && jb.pending)
+        // round prev+1 on a tile of block row/column prev, from the copies
+        tile::minplus_tile_ab<Op, NORM>(acc, a.pcol, TB, a.prow, a.ldc, i0, j0, mr, nc,
+                                        width(a.n, a.prev + 1), true, L);
+    tile::minplus_tile<Op, NORM>(acc, a.D, a.ld, i0, j0, kb, mr, nc, kw, vec, L);
+    if (MODE == kNext2 && jb.close)  // phase 1 of round r+2, fused
+        tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+    tile::store_acc<Op>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
+    if (MODE == kPanelsSnap) {
+        if (jb.I == a.r)  // block row: row k of the copy holds row k of the block
+            tile::store_acc<Op>(acc, a.srow, a.ldc, 0, j0, mr, nc, true);
+        else              // block column: rows of 128, at their matrix row
+            tile::store_acc<Op>(acc, a.scol, TB, i0, 0, mr, nc, true);
+    }
+}
+
+template <class Op, int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pair(PairArgs a) {
+    __shared__ tile::Lds L;
+    pair_update<Op, MODE, false>(a, L);
+}
+
+// int32 on the fp32 pipe (OpI32F, bit-identical) when *wmax allows it.
+template <int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_i32(
+    PairArgs a, const uint32_t *__restrict__ wmax) {
+    __shared__ tile::Lds L;
+    if (int_exact_in_f32(a.n, *wmax))
+        pair_update<OpI32F, MODE, true>(a, L);
+    else
+        pair_update<OpI32, MODE, false>(a, L);
+}
+
+template <int MODE>
+hipError_t launch(const PairArgs &a, int dtype, const uint32_t *wmax, unsigned grid,
+                  hipStream_t s) {
+    if (grid == 0) return hipSuccess;
+    if (dtype == 0 && wmax)
+        hipLaunchKernelGGL((k_pair_i32<MODE>), dim3(grid), dim3(NT), 0, s, a, wmax);
+    else if (dtype == 0)
+        hipLaunchKernelGGL((k_pair<OpI32, MODE>), dim3(grid), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pair<OpF32, MODE>), dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+PairArgs base_args(uint32_t *D, int64_t n, int64_t ld, int r, const PairCopies &c) {
+    PairArgs a{};
+    a.D = D;
+    a.ld = ld;
+    a.n = n;
+    a.r = r;
+    a.q = (int)num_rounds(n);
+    a.vec = ((reinterpret_cast<uintptr_t>(D) & 15u) == 0 && (ld & 3) == 0) ? 1 : 0;
+    const int nx = a.q - (r + 2);
+    a.nxt = nx < 0 ? 0 : (nx > 2 ? 2 : nx);
+    a.prev = -1;
+    a.ldc = c.ld;
+    return a;
+}
+
+}  // namespace
+
+int pair_next_blocks(int64_t n, int64_t r) {
+    const int64_t nx = num_rounds(n) - (r + 2);
+    return (int)(nx < 0 ? 0 : (nx > 2 ? 2 : nx));
+}
+
+int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
+    const int64_t q = num_rounds(n);
+    if (r < 0 || r + 1 >= q || lo >= hi) return 0;
+    const int64_t e1 = r + 2 + pair_next_blocks(n, r);
+    const int64_t x0 = std::max(r, lo), x1 = std::min(e1, hi);
+    const int64_t rows = hi - lo - (x1 > x0 ? x1 - x0 : 0);
+    return rows > 0 ? rows * (q - (e1 - r)) : 0;
+}
+
+hipError_t launch_pair_panels(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t pr,
+                              const PairCopies &c, int slot, hipStream_t s,
+                              const uint32_t *wmax) {
+    PairArgs a = base_args(D, n, ld, (int)pr, c);
+    a.srow = c.row[slot];
+    a.scol = c.col[slot];
+    return launch<kPanelsSnap>(a, dtype, wmax, (unsigned)(2 * (a.q - 1)), s);
+}
+
+hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                            bool close, int64_t prev, const PairCopies &c, int prev_slot,
+                            hipStream_t s, const uint32_t *wmax) {
+    PairArgs a = base_args(D, n, ld, (int)r, c);
+    a.close = close ? 1 : 0;
+    a.prev = (int)prev;
+    if (prev >= 0) {
+        a.prow = c.row[prev_slot];
+        a.pcol = c.col[prev_slot];
+    }
+    const int m = a.q - 2;
+    return launch<kNext2>(a, dtype, wmax, (unsigned)(a.nxt * m + a.nxt * (m - a.nxt)), s);
+}
+
+hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                            int64_t lo, int64_t hi, int64_t prev, const PairCopies &c,
+                            int prev_slot, hipStream_t s, const uint32_t *wmax) {
+    const int64_t count = pair_rest_count(n, r, lo, hi);
+    if (count <= 0) return hipSuccess;
+    PairArgs a = base_args(D, n, ld, (int)r, c);
+    a.lo = (int)lo;
+    a.hi = (int)hi;
+    a.prev = (int)prev;
+    if (prev >= 0) {
+        a.prow = c.row[prev_slot];
+        a.pcol = c.col[prev_slot];
+    }
+    return launch<kRest2>(a, dtype, wmax, (unsigned)count, s);
+}
+
+hipError_t launch_pair_fix(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                           bool final_, hipStream_t s, const uint32_t *wmax) {
+    PairArgs a = base_args(D, n, ld, (int)r, PairCopies{});
+    a.final_ = final_ ? 1 : 0;
+    const unsigned count = final_ ? (unsigned)((a.q - 1 - a.nxt) + (a.q - 2 - a.nxt))
+                                  : (unsigned)(2 * a.nxt);
+    return launch<kFix>(a, dtype, wmax, count, s);
+}
+
+}  // namespace apsp

@@ -55,14 +55,58 @@ constexpr int kBands = 2;
 #define APSP_MIN_BAND_ROUNDS 64
 #endif
 constexpr int64_t kMinBandRounds = APSP_MIN_BAND_ROUNDS;
+// From this many rounds on, phase 3 runs in round pairs (apsp_pair.hip):
+// one pass with k over two blocks reads and writes each tile once per two
+// rounds.  Below it the extra launches of a pair outweigh the saving.
+#ifndef APSP_MIN_PAIR_ROUNDS
+#define APSP_MIN_PAIR_ROUNDS 8
+#endif
+constexpr int64_t kMinPairRounds = APSP_MIN_PAIR_ROUNDS;
 
 struct Helper {
     hipStream_t side[kBands] = {};
     hipEvent_t p2_done = nullptr;             // recorded on S after P2(r)
     hipEvent_t rest_done[kBands] = {};        // recorded on H_g after band g of B(r)
     uint32_t *word = nullptr;                 // int32: largest finite entry of the matrix
+    PairCopies copies;                        // round pairs: copies of round r+1's panels
+    void *copies_buf = nullptr;
+    size_t copies_bytes = 0;
     std::mutex mu;                            // one solve enqueues on these at a time
 };
+
+// Point h->copies at three slots sized for n, growing the buffer if needed.
+// False when the memory is not there (the caller then runs single rounds).
+bool ensure_copies(Helper *h, int64_t n, hipStream_t s) {
+    const int64_t q = num_rounds(n);
+    const int64_t ldc = (n + 63) / 64 * 64;
+    const size_t row_elems = (size_t)kRoundB * (size_t)ldc;
+    const size_t col_elems = (size_t)q * kRoundB * kRoundB;
+    const size_t need = 3 * (row_elems + col_elems) * sizeof(uint32_t);
+    if (h->copies_bytes < need) {
+        if (h->copies_buf) {
+            // earlier solves on these streams may still read the old buffer
+            if (hipStreamSynchronize(s) != hipSuccess) return false;
+            for (hipStream_t x : h->side)
+                if (hipStreamSynchronize(x) != hipSuccess) return false;
+            (void)hipFree(h->copies_buf);
+            h->copies_buf = nullptr;
+            h->copies_bytes = 0;
+        }
+        if (hipMalloc(&h->copies_buf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            h->copies_buf = nullptr;
+            return false;
+        }
+        h->copies_bytes = need;
+    }
+    uint32_t *base = static_cast<uint32_t *>(h->copies_buf);
+    for (int k = 0; k < 3; ++k) {
+        h->copies.row[k] = base + k * (row_elems + col_elems);
+        h->copies.col[k] = h->copies.row[k] + row_elems;
+    }
+    h->copies.ld = ldc;
+    return true;
+}
 
 
 
@@ -150,29 +194,40 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     const uint32_t *wmax = dtype == 0 ? h->word : nullptr;
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
+    const bool pairs = q >= kMinPairRounds && r1 - r0 >= 2 && ensure_copies(h, n, s);
 
+    // Timing: spans of enqueued work on a stream, by category (the PhaseTimes
+    // index: 1 phase 1, 2 phase 2, 7 phase 3 on the caller's stream, 5 the
+    // bands of the rest set), from events created before anything is enqueued.
     Timer tm;
-    struct RoundEv {
-        hipEvent_t start, p1, p2, a0, a1, b0[kBands], b1[kBands];
+    struct Span {
+        int cat;
+        hipEvent_t b, e;
     };
-    std::vector<RoundEv> rev;
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> pool;
+    size_t pool_next = 0;
     hipEvent_t t_begin = nullptr, t_pro = nullptr, t_end = nullptr;
     auto rec = [&](hipEvent_t e, hipStream_t st) {
         if (e && hipEventRecord(e, st) != hipSuccess) tm.ok = false;
+    };
+    auto open = [&](int cat, hipStream_t st) -> size_t {
+        if (!times || pool_next + 2 > pool.size()) return SIZE_MAX;
+        spans.push_back(Span{cat, pool[pool_next], pool[pool_next + 1]});
+        pool_next += 2;
+        rec(spans.back().b, st);
+        return spans.size() - 1;
+    };
+    auto close = [&](size_t i, hipStream_t st) {
+        if (i != SIZE_MAX) rec(spans[i].e, st);
     };
     if (times) {
         t_begin = tm.make();
         t_pro = tm.make();
         t_end = tm.make();
-        rev.resize((size_t)(r1 - r0));
-        for (auto &e : rev) {
-            e.start = tm.make(); e.p1 = tm.make(); e.p2 = tm.make();
-            e.a0 = tm.make(); e.a1 = tm.make();
-            for (int g = 0; g < kBands; ++g) {
-                e.b0[g] = tm.make();
-                e.b1[g] = tm.make();
-            }
-        }
+        const size_t per_round = 2 * (4 + kBands);
+        pool.resize((size_t)(r1 - r0 + 2) * per_round);
+        for (auto &e : pool) e = tm.make();
         if (!tm.ok) return hipErrorOutOfMemory;
         rec(t_begin, s);
     }
@@ -189,57 +244,153 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     if (times) rec(t_pro, s);
 
     bool rest_pending = false;
-    bool diag_closed = false;  // phase 1 of round r already ran inside A(r-1)
-    for (int64_t r = r0; r < r1 && err == hipSuccess; ++r) {
-        RoundEv *e = times ? &rev[(size_t)(r - r0)] : nullptr;
-        if (e) rec(e->start, s);
+    bool diag_closed = false;  // phase 1 of round r already ran inside an earlier launch
+    int64_t rest_launches = 0;
+    auto wait_rest = [&](hipStream_t st) {
+        if (rest_pending)
+            for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(st, h->rest_done[g], 0));
+    };
+    auto band_range = [&](int g, int64_t &lo, int64_t &hi) {
+        lo = q * g / bands;  // band g: block rows [q g / bands, q (g+1) / bands)
+        hi = q * (g + 1) / bands;
+    };
+    // A round's phase 1 + 2 on S (phase 1 unless an earlier launch fused it).
+    auto phases12 = [&](int64_t r) {
+        size_t sp = open(1, s);
         if (!diag_closed) chk(launch_phase1(D, n, ld, dtype, r, s));
+        close(sp, s);
         diag_closed = false;
-        if (e) rec(e->p1, s);
+        sp = open(2, s);
         chk(launch_tile_set(D, n, ld, dtype, r, kPanels, s, false, wmax));
-        if (e) rec(e->p2, s);
-        if (lookahead && r + 1 < q) {
-            // Fuse phase 1 of round r+1 into A(r) unless this call stops after
-            // round r: a solve split over calls leaves exactly the state of
-            // Floyd-Warshall after its last round's pivots.
-            const bool fuse = r + 1 < r1;
+        close(sp, s);
+    };
+
+    if (pairs) {
+        // Round pairs (r, r+1), see apsp_pair.hip.  On S: phases 1-2 of
+        // round r, round r's phase 3 on block row/column r+1 with the
+        // closure of block r+1, phase 2 of round r+1 (copied to a slot);
+        // then, after the previous pair's rest set, the pair pass on block
+        // rows/columns r+2, r+3 (closing block r+2) and the deferred updates
+        // of tiles (x, r), (r, x).  The rest set runs in bands on the helper
+        // streams as soon as phase 2 of round r+1 is done.  A band that
+        // holds block row prev or prev+1 (the previous pair) waits for every
+        // band of the previous pair: all of them read those rows.
+        int64_t prev = -1;
+        int prev_slot = 0, slot = 0;
+        int64_t r = r0;
+        while (r < r1 && err == hipSuccess) {
+            if (r + 1 >= r1) {  // the call's last round alone
+                wait_rest(s);
+                rest_pending = false;
+                if (prev >= 0) {
+                    const size_t sp = open(7, s);
+                    chk(launch_pair_fix(D, n, ld, dtype, prev, true, s, wmax));
+                    close(sp, s);
+                    prev = -1;
+                }
+                phases12(r);
+                const size_t sp = open(7, s);
+                chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
+                close(sp, s);
+                ++r;
+                break;
+            }
+            const int nx = pair_next_blocks(n, r);
+            phases12(r);
+            size_t sp = open(7, s);
+            chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, true, wmax));
+            close(sp, s);
+            sp = open(2, s);
+            chk(launch_pair_panels(D, n, ld, dtype, r + 1, h->copies, slot, s, wmax));
+            close(sp, s);
             chk(hipEventRecord(h->p2_done, s));
-            if (rest_pending)
-                for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
-            if (e) rec(e->a0, s);
-            chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse, wmax));
-            if (e) rec(e->a1, s);
-            diag_closed = fuse;
+            wait_rest(s);
+            const bool close_next = nx > 0 && r + 2 < r1;
+            sp = open(7, s);
+            if (nx > 0) {
+                chk(launch_pair_next(D, n, ld, dtype, r, close_next, prev, h->copies, prev_slot,
+                                     s, wmax));
+                chk(launch_pair_fix(D, n, ld, dtype, r, false, s, wmax));
+            }
+            close(sp, s);
+            diag_closed = close_next;
             for (int g = 0; g < bands; ++g) {
-                // band g: block rows [q g / bands, q (g+1) / bands)
-                const int64_t lo = q * g / bands, hi = q * (g + 1) / bands;
-                // Block row r-1 was the row panel every band of B(r-1) read;
-                // the band that now updates it waits for all of B(r-1).  (The
-                // events still hold round r-1: this round records them below.)
-                if (rest_pending && r - 1 >= lo && r - 1 < hi)
+                int64_t lo, hi;
+                band_range(g, lo, hi);
+                if (rest_pending && prev >= 0 &&
+                    ((prev >= lo && prev < hi) || (prev + 1 >= lo && prev + 1 < hi)))
                     for (int o = 0; o < bands; ++o)
                         if (o != g) chk(hipStreamWaitEvent(h->side[g], h->rest_done[o], 0));
             }
             for (int g = 0; g < bands; ++g) {
-                const int64_t lo = q * g / bands, hi = q * (g + 1) / bands;
+                int64_t lo, hi;
+                band_range(g, lo, hi);
                 chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
-                if (e) rec(e->b0[g], h->side[g]);
-                chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g], wmax));
-                if (e) rec(e->b1[g], h->side[g]);
+                const size_t b = open(5, h->side[g]);
+                chk(launch_pair_rest(D, n, ld, dtype, r, lo, hi, prev, h->copies, prev_slot,
+                                     h->side[g], wmax));
+                close(b, h->side[g]);
                 chk(hipEventRecord(h->rest_done[g], h->side[g]));
             }
             rest_pending = true;
-        } else {
-            if (rest_pending)
-                for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
-            rest_pending = false;
-            if (e) rec(e->a0, s);
-            chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
-            if (e) rec(e->a1, s);
+            ++rest_launches;
+            prev = r;
+            prev_slot = slot;
+            slot = (slot + 1) % 3;
+            r += 2;
         }
+        wait_rest(s);
+        if (prev >= 0 && err == hipSuccess) {
+            const size_t sp = open(7, s);
+            chk(launch_pair_fix(D, n, ld, dtype, prev, true, s, wmax));
+            close(sp, s);
+        }
+    } else {
+        for (int64_t r = r0; r < r1 && err == hipSuccess; ++r) {
+            phases12(r);
+            if (lookahead && r + 1 < q) {
+                // Fuse phase 1 of round r+1 into A(r) unless this call stops
+                // after round r: a solve split over calls leaves exactly the
+                // state of Floyd-Warshall after its last round's pivots.
+                const bool fuse = r + 1 < r1;
+                chk(hipEventRecord(h->p2_done, s));
+                wait_rest(s);
+                size_t sp = open(7, s);
+                chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse, wmax));
+                close(sp, s);
+                diag_closed = fuse;
+                for (int g = 0; g < bands; ++g) {
+                    int64_t lo, hi;
+                    band_range(g, lo, hi);
+                    // Block row r-1 was the row panel every band of B(r-1)
+                    // read; the band that now updates it waits for all of
+                    // B(r-1).  (The events still hold round r-1: this round
+                    // records them below.)
+                    if (rest_pending && r - 1 >= lo && r - 1 < hi)
+                        for (int o = 0; o < bands; ++o)
+                            if (o != g) chk(hipStreamWaitEvent(h->side[g], h->rest_done[o], 0));
+                }
+                for (int g = 0; g < bands; ++g) {
+                    int64_t lo, hi;
+                    band_range(g, lo, hi);
+                    chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
+                    const size_t b = open(5, h->side[g]);
+                    chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g], wmax));
+                    close(b, h->side[g]);
+                    chk(hipEventRecord(h->rest_done[g], h->side[g]));
+                }
+                rest_pending = true;
+                ++rest_launches;
+            } else {
+                wait_rest(s);
+                rest_pending = false;
+                const size_t sp = open(7, s);
+                chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
+                close(sp, s);
+            }
+        }
+        wait_rest(s);
     }
-    if (rest_pending)
-        for (int g = 0; g < bands; ++g) chk(hipStreamWaitEvent(s, h->rest_done[g], 0));
     if (err != hipSuccess) return err;
     if (!times) return hipSuccess;
 
@@ -248,23 +399,18 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     if ((err = hipEventSynchronize(t_end)) != hipSuccess) return err;
     double *m = times->ms;
     m[0] = elapsed(t_begin, t_pro);
-    // B: the time during which any band of any round ran (the union of the
-    // band launches' intervals; bands of consecutive rounds overlap)
-    std::vector<std::pair<double, double>> spans;
-    for (int64_t r = r0; r < r1; ++r) {
-        const RoundEv &e = rev[(size_t)(r - r0)];
-        m[1] += elapsed(e.start, e.p1);
-        m[2] += elapsed(e.p1, e.p2);
-        m[7] += elapsed(e.a0, e.a1);
-        if (lookahead && r + 1 < q) {
-            for (int g = 0; g < bands; ++g)
-                spans.emplace_back(elapsed(t_begin, e.b0[g]), elapsed(t_begin, e.b1[g]));
-            m[6] += 1.0;
-        }
+    // rest set: the time during which any band launch ran (the union of their
+    // intervals; bands of consecutive rounds or pairs overlap)
+    std::vector<std::pair<double, double>> bspans;
+    for (const Span &sp : spans) {
+        if (sp.cat == 5)
+            bspans.emplace_back(elapsed(t_begin, sp.b), elapsed(t_begin, sp.e));
+        else
+            m[sp.cat] += elapsed(sp.b, sp.e);
     }
-    std::sort(spans.begin(), spans.end());
+    std::sort(bspans.begin(), bspans.end());
     double cover = 0.0, lo = 0.0, hi = -1.0;
-    for (const auto &sp : spans) {
+    for (const auto &sp : bspans) {
         if (sp.first > hi) {
             if (hi > lo) cover += hi - lo;
             lo = sp.first;
@@ -275,6 +421,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     }
     if (hi > lo) cover += hi - lo;
     m[5] = cover;
+    m[6] = (double)rest_launches;
     m[3] = m[7] + cover;
     m[4] = elapsed(t_begin, t_end);
     return hipSuccess;

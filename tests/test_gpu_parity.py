@@ -359,6 +359,68 @@ def test_banded_ragged_int32_rows(apsp, dev, whi):
     assert oracle.bellman_violations_i32(D.cpu().numpy(), csr, brows, threads=16) == 0
 
 
+# ------------------------------------------------------------ round pairs
+# From 8 rounds on, phase 3 runs in pairs of rounds, with round r+1's update
+# of the pair's first block row/column deferred.  These cases cross every
+# boundary of that schedule: odd and even round counts, calls that stop
+# after either round of a pair or resume in the middle of one, and the next
+# pair's blocks being absent or half present.  fp32 results must equal the
+# blocked model bit for bit.
+
+@pytest.mark.parametrize("n", [1024, 1100, 1300, 2100])
+def test_pair_schedule_fp32_bitexact(apsp, dev, n):
+    """q = 8, 9, 11, 17 rounds: the whole solve equals the blocked model."""
+    W, _ = _swiss(n, 40 + n)
+    assert apsp.num_rounds(n) >= 8
+    assert np.array_equal(_solve(apsp, W, dev), oracle.blocked(W, 128))
+
+
+@pytest.mark.parametrize("r0,r1", [(0, 3), (0, 4), (0, 7), (1, 6), (3, 10), (5, 12), (2, 11),
+                                   (10, 12), (4, 12)])
+def test_pair_schedule_slices_fp32(apsp, dev, r0, r1):
+    """n = 1500 (12 rounds): rounds r0..r1-1, started from the blocked model's
+    state after r0 rounds, leave the model's state after r1 rounds."""
+    import torch
+
+    n = 1500
+    W, _ = _swiss(n, 60)
+    start = W if r0 == 0 else oracle.blocked(W, 128, 0, r0)
+    view, _ = _to_dev(start, dev)
+    apsp.solve_rounds(view, r0, r1)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy(), oracle.blocked(start, 128, r0, r1))
+
+
+@pytest.mark.parametrize("whi", [100, 1 << 20])
+def test_pair_schedule_int32(apsp, dev, whi):
+    """int32, n = 1200 (10 rounds), on either pipe: a solve split after
+    rounds 3 and 8 passes through Floyd-Warshall's states after 3*128 and
+    8*128 pivots and ends at the oracle's result."""
+    import torch
+
+    n = 1200
+    W, _ = _er(n, 5.0 / n, 70 + whi, 1, whi)
+    view, _ = _to_dev(W, dev)
+    for r0, r1 in ((0, 3), (3, 8), (8, 10)):
+        apsp.solve_rounds(view, r0, r1)
+        torch.cuda.synchronize()
+        ref = oracle.fw_steps(oracle.prepare(W), 0, min(r1 * 128, n), threads=8)
+        assert np.array_equal(view.cpu().numpy().astype(np.int64), np.minimum(ref, INF)), r1
+
+
+def test_pair_schedule_profiled(apsp, dev):
+    """The profiled solve runs the same schedule (one rest launch group per
+    pair of rounds) and gives the same result."""
+    n = 1200
+    W, _ = _swiss(n, 75)
+    a = _solve(apsp, W, dev)
+    view, _ = _to_dev(W, dev)
+    t = apsp.solve_profiled(view)
+    assert np.array_equal(view.cpu().numpy(), a)
+    assert t["phase3_rest_launches"] == apsp.num_rounds(n) // 2
+    assert t["phase3_rest"] > 0 and t["total"] > 0
+
+
 # --------------------------------------------------------------- batched
 
 def _batched_case_sizes():
