@@ -81,7 +81,15 @@ enum {
  * forms is an integer below 2^24, and the tiles are computed in fp32
  * arithmetic (exact, so the result is the same) at its higher issue rate.
  * The scan's result lives in a 256-byte device word allocated with the
- * helper streams.  Nothing else is allocated.
+ * helper streams.  From 8 rounds up (n > 896), phase 3 runs in pairs of
+ * rounds: one pass per tile with k over both rounds' blocks, the second
+ * round's update of the first round's block row and column deferred and
+ * applied from a copy of its panels (the result is the same, bit for bit).
+ * The copies take 3 x (128 x ceil64(n) + 128 x 128 x q) x 4 bytes (48 MiB at
+ * n = 16384, 768 MiB at n = 262144), allocated with the helper streams on
+ * first need and grown (after synchronising those streams) for a larger n;
+ * when they cannot be allocated the call runs single rounds instead.
+ * Nothing else is allocated.
  * Solves enqueued on the same stream from several host threads are
  * serialised by the library.
  * Returns APSP_OK, APSP_ERR_INVALID_VALUE, APSP_ERR_NO_MEMORY (helper stream
@@ -108,11 +116,14 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
  *   [0] input normalisation (ms)
  *   [1] phase 1, summed over rounds        [2] phase 2, summed over rounds
  *   [3] phase 3: [5] + [7]                 [4] the whole solve
- *   [5] the time during which the phase-3 tiles outside block row/column
- *       r+1 were being updated: they run as bands of block rows on helper
- *       streams, bands of consecutive rounds overlapping, and [5] is the
- *       union of those launches' intervals   [6] how many rounds had them
- *   [7] the other phase-3 launches (block row/column r+1), summed
+ *   [5] the time during which the bulk of phase 3 was being updated (the
+ *       tiles outside block rows/columns r .. r+3 of a pair of rounds, or
+ *       outside r, r+1 of a single round): it runs as bands of block rows on
+ *       helper streams, bands of consecutive pairs or rounds overlapping,
+ *       and [5] is the union of those launches' intervals
+ *   [6] how many pairs of rounds (or single rounds) had such launches
+ *   [7] the other phase-3 launches on `stream` (block rows/columns r+1 ..
+ *       r+3 and the deferred updates), summed
  * Phase-3 launches overlap phases 1 and 2 of the next round (one-round
  * lookahead), so [1] + [2] + [3] can exceed [4].  The result in `dist` is
  * identical to apsp_solve's.  phase_ms must have room for 8 values.
