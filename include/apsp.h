@@ -81,8 +81,8 @@ enum {
  * forms is an integer below 2^24, and the tiles are computed in fp32
  * arithmetic (exact, so the result is the same) at its higher issue rate.
  * The scan's result lives in a 256-byte device word allocated with the
- * helper streams.  From 8 rounds up (n > 896), phase 3 runs in pairs of
- * rounds: one pass per tile with k over both rounds' blocks, the second
+ * helper streams.  From 72 rounds up (n > 9088; apsp_set_round_pair_threshold),
+ * phase 3 runs in pairs of rounds: one pass per tile with k over both rounds' blocks, the second
  * round's update of the first round's block row and column deferred and
  * applied from a copy of its panels (the result is the same, bit for bit).
  * The copies take 3 x (128 x ceil64(n) + 128 x 128 x q) x 4 bytes (48 MiB at
@@ -96,6 +96,19 @@ enum {
  * could not be created) or APSP_ERR_DEVICE.
  */
 int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
+
+/*
+ * apsp_set_round_pair_threshold -- the number of rounds q = ceil(n/b) from
+ * which apsp_solve, apsp_solve_rounds (for a call of two or more rounds) and
+ * apsp_solve_profiled run phase 3 in pairs of rounds (see apsp_solve;
+ * default 72: measured on MI355X, pairs lose 6% at 64 rounds, where the
+ * pair's longer chain of launches on the caller's stream is not hidden, and
+ * win 2% at 72 and 7% at 128).  The results are the same either way.
+ * rounds >= 2; a value above any q disables pairs.  Process-wide, takes
+ * effect for solves enqueued afterwards; no HIP call.
+ * Returns the previous threshold, or -1 (unchanged) when rounds < 2.
+ */
+int32_t apsp_set_round_pair_threshold(int32_t rounds);
 
 /*
  * apsp_solve_rounds -- run rounds r0 .. r1-1 of the blocked method only

@@ -63,6 +63,7 @@ def _load() -> ctypes.CDLL:
         "apsp_solve_profiled": ([vp, i64, i64, i32, vp, ctypes.POINTER(ctypes.c_double)], i32),
         "apsp_round_width": ([i64, i32], i32),
         "apsp_batched_round_width": ([i64, i32], i32),
+        "apsp_set_round_pair_threshold": ([i32], i32),
         "apsp_solve_batched": ([vp, vp, i32, vp], i32),
         "apsp_solve_batched_ex": ([vp, vp, vp, i32, i32, vp], i32),
         "apsp_validate": ([vp, i64, i64, i32, vp], i32),
@@ -138,6 +139,15 @@ def _stream(stream):
 def _check(status: int, what: str):
     if status != 0:
         raise ApspError(status, what)
+
+
+def set_round_pair_threshold(rounds: int) -> int:
+    """Rounds from which solves run phase 3 in round pairs (process-wide;
+    default 72); returns the previous value.  The results are the same."""
+    prev = int(_LIB.apsp_set_round_pair_threshold(int(rounds)))
+    if prev < 0:
+        raise ValueError("the threshold is a number of rounds >= 2")
+    return prev
 
 
 def round_width(n: int = 0, dtype: int = APSP_F32) -> int:

@@ -79,6 +79,11 @@ int32_t apsp_round_width(int64_t, int32_t dtype) {
     return bad_dtype(dtype) ? 0 : apsp::kRoundB;
 }
 
+int32_t apsp_set_round_pair_threshold(int32_t rounds) {
+    if (rounds < 2) return -1;
+    return (int32_t)apsp::set_pair_rounds(rounds);
+}
+
 int32_t apsp_batched_round_width(int64_t n, int32_t dtype) {
     return bad_dtype(dtype) ? 0 : apsp::batched_tile(n);
 }

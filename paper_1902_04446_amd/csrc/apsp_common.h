@@ -223,5 +223,7 @@ struct PhaseTimes {
 // timing; the call then waits for completion before filling it in.
 hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0, int64_t r1,
                       bool prologue, hipStream_t s, PhaseTimes *times);
+// Rounds from which run_rounds uses round pairs; returns the previous value.
+int64_t set_pair_rounds(int64_t rounds);
 
 }  // namespace apsp

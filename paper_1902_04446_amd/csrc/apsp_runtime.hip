@@ -33,6 +33,7 @@
 // The result is the same as running the three phases in order, bit for bit:
 // every tile sees the same operands in the same round.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -57,11 +58,12 @@ constexpr int kBands = 2;
 constexpr int64_t kMinBandRounds = APSP_MIN_BAND_ROUNDS;
 // From this many rounds on, phase 3 runs in round pairs (apsp_pair.hip):
 // one pass with k over two blocks reads and writes each tile once per two
-// rounds.  Below it the extra launches of a pair outweigh the saving.
-#ifndef APSP_MIN_PAIR_ROUNDS
-#define APSP_MIN_PAIR_ROUNDS 8
-#endif
-constexpr int64_t kMinPairRounds = APSP_MIN_PAIR_ROUNDS;
+// rounds.  Below it the pair's longer chain of launches on the caller's
+// stream is not hidden behind the rest set: measured, pairs lose 6% at 64
+// rounds and win 2% at 72, 7% at 128.  Settable per process
+// (apsp_set_round_pair_threshold).
+constexpr int64_t kDefaultPairRounds = 72;
+std::atomic<int64_t> g_pair_rounds{kDefaultPairRounds};
 
 struct Helper {
     hipStream_t side[kBands] = {};
@@ -194,7 +196,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     const uint32_t *wmax = dtype == 0 ? h->word : nullptr;
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
-    const bool pairs = q >= kMinPairRounds && r1 - r0 >= 2 && ensure_copies(h, n, s);
+    const bool pairs = q >= g_pair_rounds.load() && r1 - r0 >= 2 && ensure_copies(h, n, s);
 
     // Timing: spans of enqueued work on a stream, by category (the PhaseTimes
     // index: 1 phase 1, 2 phase 2, 7 phase 3 on the caller's stream, 5 the
@@ -426,5 +428,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     m[4] = elapsed(t_begin, t_end);
     return hipSuccess;
 }
+
+int64_t set_pair_rounds(int64_t rounds) { return g_pair_rounds.exchange(rounds); }
 
 }  // namespace apsp

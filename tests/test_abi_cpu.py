@@ -180,6 +180,17 @@ def test_status_strings_and_widths(lib):
     assert b"gfx950" in lib.apsp_version()
 
 
+def test_round_pair_threshold_setter(lib):
+    """No HIP call: the setter swaps a process-wide value and rejects < 2."""
+    prev = lib.apsp_set_round_pair_threshold(9)
+    try:
+        assert prev >= 2
+        assert lib.apsp_set_round_pair_threshold(1) == -1
+        assert lib.apsp_set_round_pair_threshold(10) == 9
+    finally:
+        lib.apsp_set_round_pair_threshold(prev)
+
+
 def test_binding_rejects_host_tensors():
     import torch
 

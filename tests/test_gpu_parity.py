@@ -333,13 +333,23 @@ def test_int32_slices_switch_pipes(apsp, dev):
     assert np.array_equal(part.astype(np.int64), oracle.fw(W, threads=4))
 
 
+@pytest.mark.parametrize("pairs", [False, True])
 @pytest.mark.parametrize("whi", [100, 1 << 20])
-def test_banded_ragged_int32_rows(apsp, dev, whi):
-    """n = 8300: 65 rounds, so phase 3 runs as two bands of block rows with the
-    one-round lookahead, and the last block is partial (8300 = 64 * 128 + 108).
-    U{1..100} takes the fp32 pipe, U{1..2^20} uint32.  Sampled rows and
-    columns (the last vertex among them) equal the oracle's Dijkstra exactly,
-    and the exact Bellman certificate holds on a larger sample of rows."""
+def test_banded_ragged_int32_rows(apsp, dev, whi, pairs):
+    """n = 8300: 65 rounds, so phase 3 runs as two bands of block rows, in
+    single rounds or (threshold lowered) in round pairs ending with a round
+    alone, and the last block is partial (8300 = 64 * 128 + 108).  U{1..100}
+    takes the fp32 pipe, U{1..2^20} uint32.  Sampled rows and columns (the
+    last vertex among them) equal the oracle's Dijkstra exactly, and the
+    exact Bellman certificate holds on a larger sample of rows."""
+    prev = apsp.set_round_pair_threshold(8 if pairs else 1000)
+    try:
+        _banded_ragged(apsp, dev, whi)
+    finally:
+        apsp.set_round_pair_threshold(prev)
+
+
+def _banded_ragged(apsp, dev, whi):
     import torch
 
     n = 8300
@@ -360,15 +370,23 @@ def test_banded_ragged_int32_rows(apsp, dev, whi):
 
 
 # ------------------------------------------------------------ round pairs
-# From 8 rounds on, phase 3 runs in pairs of rounds, with round r+1's update
-# of the pair's first block row/column deferred.  These cases cross every
-# boundary of that schedule: odd and even round counts, calls that stop
-# after either round of a pair or resume in the middle of one, and the next
-# pair's blocks being absent or half present.  fp32 results must equal the
-# blocked model bit for bit.
+# From 72 rounds on (by default), phase 3 runs in pairs of rounds, with round
+# r+1's update of the pair's first block row/column deferred.  The threshold
+# is lowered to 8 rounds here so small matrices take that schedule.  These
+# cases cross every boundary of it: odd and even round counts, calls that
+# stop after either round of a pair or resume in the middle of one, and the
+# next pair's blocks being absent or half present.  fp32 results must equal
+# the blocked model bit for bit.
+
+@pytest.fixture
+def pairs_from_8(apsp):
+    prev = apsp.set_round_pair_threshold(8)
+    yield
+    apsp.set_round_pair_threshold(prev)
+
 
 @pytest.mark.parametrize("n", [1024, 1100, 1300, 2100])
-def test_pair_schedule_fp32_bitexact(apsp, dev, n):
+def test_pair_schedule_fp32_bitexact(apsp, dev, pairs_from_8, n):
     """q = 8, 9, 11, 17 rounds: the whole solve equals the blocked model."""
     W, _ = _swiss(n, 40 + n)
     assert apsp.num_rounds(n) >= 8
@@ -377,7 +395,7 @@ def test_pair_schedule_fp32_bitexact(apsp, dev, n):
 
 @pytest.mark.parametrize("r0,r1", [(0, 3), (0, 4), (0, 7), (1, 6), (3, 10), (5, 12), (2, 11),
                                    (10, 12), (4, 12)])
-def test_pair_schedule_slices_fp32(apsp, dev, r0, r1):
+def test_pair_schedule_slices_fp32(apsp, dev, pairs_from_8, r0, r1):
     """n = 1500 (12 rounds): rounds r0..r1-1, started from the blocked model's
     state after r0 rounds, leave the model's state after r1 rounds."""
     import torch
@@ -392,7 +410,7 @@ def test_pair_schedule_slices_fp32(apsp, dev, r0, r1):
 
 
 @pytest.mark.parametrize("whi", [100, 1 << 20])
-def test_pair_schedule_int32(apsp, dev, whi):
+def test_pair_schedule_int32(apsp, dev, pairs_from_8, whi):
     """int32, n = 1200 (10 rounds), on either pipe: a solve split after
     rounds 3 and 8 passes through Floyd-Warshall's states after 3*128 and
     8*128 pivots and ends at the oracle's result."""
@@ -408,9 +426,9 @@ def test_pair_schedule_int32(apsp, dev, whi):
         assert np.array_equal(view.cpu().numpy().astype(np.int64), np.minimum(ref, INF)), r1
 
 
-def test_pair_schedule_profiled(apsp, dev):
+def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
     """The profiled solve runs the same schedule (one rest launch group per
-    pair of rounds) and gives the same result."""
+    pair of rounds) and gives the same result as single rounds."""
     n = 1200
     W, _ = _swiss(n, 75)
     a = _solve(apsp, W, dev)
@@ -419,6 +437,11 @@ def test_pair_schedule_profiled(apsp, dev):
     assert np.array_equal(view.cpu().numpy(), a)
     assert t["phase3_rest_launches"] == apsp.num_rounds(n) // 2
     assert t["phase3_rest"] > 0 and t["total"] > 0
+    prev = apsp.set_round_pair_threshold(1000)  # single rounds
+    try:
+        assert np.array_equal(_solve(apsp, W, dev), a)
+    finally:
+        apsp.set_round_pair_threshold(prev)
 
 
 # --------------------------------------------------------------- batched
