@@ -390,3 +390,35 @@ def test_pair_schedule_model_catches_a_missing_wait():
         m.run()
         differs += not np.array_equal(D.view(np.int32), ref.view(np.int32))
     assert differs > 0
+
+
+@pytest.mark.parametrize("n", [1024, 1100, 2100, 5000, 16384])
+def test_bench_pair_update_count(n):
+    """bench.py's algorithmic update count of the pair rest launches (the
+    roofline numerator) equals a count over the tiles the maps above assign,
+    with their widths, including the deferred updates."""
+    import importlib.util
+    import os
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    b = 128
+    q = -(-n // b)
+
+    def w(x):
+        return min(b, n - x * b)
+
+    total, pairs, r, prev = 0, 0, 0, -1
+    while r + 1 < q:
+        for g in range(2):
+            lo, hi = q * g // 2, q * (g + 1) // 2
+            for wg in range(_rest2_count(r, q, lo, hi)):
+                i, j = _rest2_tile(wg, r, q, lo, hi)
+                total += w(i) * w(j) * (w(r) + w(r + 1))
+                if _pending(i, j, prev):
+                    total += w(i) * w(j) * w(prev + 1)
+        pairs += 1
+        prev, r = r, r + 2
+    assert bench.phase3_pair_updates(n, b) == (total, pairs)
