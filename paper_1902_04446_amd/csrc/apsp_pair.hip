@@ -162,8 +162,10 @@ __device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
     const int kw = (int)(kwl < (int64_t)jb.kblocks * TB ? kwl : (int64_t)jb.kblocks * TB);
     const bool vec = a.vec != 0;
 
+    // the rest set's tiles are each read and written once per pair: stream them
+    constexpr bool kStream = MODE == kRest2;
     uint32_t acc[8][8];
-    tile::load_acc<Op, NORM>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
+    tile::load_acc<Op, NORM, kStream>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
     if (MODE != kPanelsSnap && MODE != kFix && jb.pending)
         // round prev+1 on a tile of block row/column prev, from the copies
         tile::minplus_tile_ab<Op, NORM>(acc, a.pcol, TB, a.prow, a.ldc, i0, j0, mr, nc,
@@ -171,7 +173,7 @@ __device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
     tile::minplus_tile<Op, NORM>(acc, a.D, a.ld, i0, j0, kb, mr, nc, kw, vec, L);
     if (MODE == kNext2 && jb.close)  // phase 1 of round r+2, fused
         tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
-    tile::store_acc<Op>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
+    tile::store_acc<Op, kStream>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
     if (MODE == kPanelsSnap) {
         if (jb.I == a.r)  // block row: row k of the copy holds row k of the block
             tile::store_acc<Op>(acc, a.srow, a.ldc, 0, j0, mr, nc, true);

@@ -29,6 +29,19 @@ __device__ __forceinline__ uint4 ld4(const uint32_t *p) {
 }
 __device__ __forceinline__ void st4(uint32_t *p, uint4 v) { *reinterpret_cast<uint4 *>(p) = v; }
 
+// Non-temporal 16-byte load/store (nt bit): for output tiles that are read
+// and written once per pass, so they do not evict panel blocks other
+// workgroups still read from L2.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld4_stream(const uint32_t *p) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4_stream(uint32_t *p, uint4 v) {
+    const u32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+}
+
 __device__ __forceinline__ int row_of(int m, int ty) { return (m >> 2) * 64 + ty * 4 + (m & 3); }
 __device__ __forceinline__ int col_of(int e, int tx) { return (e >> 2) * 64 + tx * 4 + (e & 3); }
 
@@ -36,7 +49,8 @@ __device__ __forceinline__ int col_of(int e, int tx) { return (e >> 2) * 64 + tx
 // "no edge".  NORM applies the input normalisation on the way in (Op::norm:
 // int32 values above 2^30 -> 2^30, or the conversion of OpI32F; a tile on the
 // diagonal gets a zero diagonal).  store_acc converts back with Op::out.
-template <class Op, bool NORM>
+// STREAM: non-temporal loads (see ld4_stream).
+template <class Op, bool NORM, bool STREAM = false>
 __device__ __forceinline__ void load_acc(uint32_t (&acc)[8][8], const uint32_t *D, int64_t ld,
                                          int64_t i0, int64_t j0, int mr, int nc, bool vec) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
@@ -49,7 +63,7 @@ __device__ __forceinline__ void load_acc(uint32_t (&acc)[8][8], const uint32_t *
         for (int h = 0; h < 2; ++h) {
             const int col = h * 64 + tx * 4;
             if (vec && row < mr && col + 3 < nc) {
-                const uint4 c4 = ld4(crow + col);
+                const uint4 c4 = STREAM ? ld4_stream(crow + col) : ld4(crow + col);
                 acc[m][h * 4 + 0] = c4.x;
                 acc[m][h * 4 + 1] = c4.y;
                 acc[m][h * 4 + 2] = c4.z;
@@ -78,7 +92,7 @@ __device__ __forceinline__ void load_acc(uint32_t (&acc)[8][8], const uint32_t *
     }
 }
 
-template <class Op>
+template <class Op, bool STREAM = false>
 __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t *D, int64_t ld,
                                           int64_t i0, int64_t j0, int mr, int nc, bool vec) {
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
@@ -91,8 +105,12 @@ __device__ __forceinline__ void store_acc(const uint32_t (&acc)[8][8], uint32_t 
         for (int h = 0; h < 2; ++h) {
             const int col = h * 64 + tx * 4;
             if (vec && col + 3 < nc) {
-                st4(crow + col, make_uint4(Op::out(acc[m][h * 4 + 0]), Op::out(acc[m][h * 4 + 1]),
-                                           Op::out(acc[m][h * 4 + 2]), Op::out(acc[m][h * 4 + 3])));
+                const uint4 o4 = make_uint4(Op::out(acc[m][h * 4 + 0]), Op::out(acc[m][h * 4 + 1]),
+                                            Op::out(acc[m][h * 4 + 2]), Op::out(acc[m][h * 4 + 3]));
+                if (STREAM)
+                    st4_stream(crow + col, o4);
+                else
+                    st4(crow + col, o4);
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
