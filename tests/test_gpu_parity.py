@@ -426,6 +426,32 @@ def test_pair_schedule_int32(apsp, dev, pairs_from_8, whi):
         assert np.array_equal(view.cpu().numpy().astype(np.int64), np.minimum(ref, INF)), r1
 
 
+@pytest.mark.parametrize("ld_extra,offset", [(3, 1), (212, 0)])
+def test_pair_schedule_layout(apsp, dev, pairs_from_8, ld_extra, offset):
+    """Round pairs on a padded or misaligned matrix (ld = n + 3 with a 4-byte
+    offset: the unaligned load path; ld = n + 212): the result equals the
+    oracle (int32) and the blocked model (fp32), and nothing outside the
+    n x n view is written."""
+    import torch
+
+    n = 1100
+    Wi, _ = _er(n, 5.0 / n, 90)
+    Wf, _ = _swiss(n, 91)
+    for W in (Wi, Wf):
+        view, buf = _to_dev(W, dev, ld=n + ld_extra, offset=offset)
+        before = buf.clone()
+        apsp.solve(view)
+        torch.cuda.synchronize()
+        got = view.cpu().numpy()
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8))
+        else:
+            assert np.array_equal(got, oracle.blocked(W, 128))
+        mask = torch.ones_like(buf, dtype=torch.bool)
+        mask[offset:offset + n * (n + ld_extra)].view(n, n + ld_extra)[:, :n] = False
+        assert torch.equal(buf[mask], before[mask])
+
+
 def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
     """The profiled solve runs the same schedule (one rest launch group per
     pair of rounds) and gives the same result as single rounds."""
