@@ -452,6 +452,32 @@ def test_pair_schedule_layout(apsp, dev, pairs_from_8, ld_extra, offset):
         assert torch.equal(buf[mask], before[mask])
 
 
+def test_pair_schedule_random_slices(apsp, dev, pairs_from_8):
+    """Eight seeded cases: n in [900, 2600), int32 or fp32, the solve cut into
+    slices at random rounds; equal to the oracle (int32) and the blocked model
+    (fp32)."""
+    import torch
+
+    rng = np.random.default_rng(2024)
+    for case in range(8):
+        n = int(rng.integers(900, 2600))
+        q = apsp.num_rounds(n)
+        if case % 2:
+            W, _ = _swiss(n, 500 + case)
+        else:
+            W, _ = _er(n, 5.0 / n, 500 + case, 1, int(rng.choice([100, 1 << 20])))
+        cuts = sorted({0, q, *(int(x) for x in rng.integers(1, q, size=int(rng.integers(0, 3))))})
+        view, _ = _to_dev(W, dev)
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            apsp.solve_rounds(view, a, b)
+        torch.cuda.synchronize()
+        got = view.cpu().numpy()
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8)), (n, cuts)
+        else:
+            assert np.array_equal(got, oracle.blocked(W, 128)), (n, cuts)
+
+
 def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
     """The profiled solve runs the same schedule (one rest launch group per
     pair of rounds) and gives the same result as single rounds."""
