@@ -122,7 +122,8 @@ __global__ void k_fill_words(uint32_t *p, int32_t count, uint32_t v) {
 
 // wmax[graph] = max(wmax[graph], largest finite (< 2^30) off-diagonal entry
 // of the item's 128 x 128 tile).  Each wave reads two tile rows per step, 16
-// bytes per lane (coalesced 512-byte row segments).
+// bytes per lane (coalesced 512-byte row segments); a thread's 16 rows are
+// loaded before any is reduced, so they are all in flight at once.
 __global__ __launch_bounds__(NT) void k_batched_wmax(const BatchDesc *__restrict__ descs,
                                                      const BatchItem *__restrict__ items,
                                                      XcdRanges ranges, uint32_t *wmax) {
@@ -134,22 +135,32 @@ __global__ __launch_bounds__(NT) void k_batched_wmax(const BatchDesc *__restrict
     const int I = it.ij >> 16, J = it.ij & 0xffff;
     const int t = threadIdx.x;
     const int c = J * TB + (t & 31) * 4;  // first of this lane's 4 columns
-    uint32_t m = 0;
-    for (int rr = t >> 5; rr < TB; rr += NT / 32) {
-        const int row = I * TB + rr;
-        if (row >= g.n) break;
-        const uint32_t *src = g.ptr + (int64_t)row * g.ld;
-        uint32_t v[4];
-        if (vec && c + 4 <= g.n) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(src + c);
-            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-        } else {
+    constexpr int kSteps = TB / (NT / 32);  // 16 rows per thread
+    uint4 v[kSteps];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = c + e < g.n ? src[c + e] : 0u;
+    for (int u = 0; u < kSteps; ++u) {
+        const int row = I * TB + (t >> 5) + u * (NT / 32);
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (row < g.n) {
+            const uint32_t *src = g.ptr + (int64_t)row * g.ld;
+            if (vec && c + 4 <= g.n) {
+                v[u] = *reinterpret_cast<const uint4 *>(src + c);
+            } else {
+                v[u].x = c + 0 < g.n ? src[c + 0] : 0u;
+                v[u].y = c + 1 < g.n ? src[c + 1] : 0u;
+                v[u].z = c + 2 < g.n ? src[c + 2] : 0u;
+                v[u].w = c + 3 < g.n ? src[c + 3] : 0u;
+            }
         }
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+        const int row = I * TB + (t >> 5) + u * (NT / 32);
+        const uint32_t e4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (v[e] < kInfI32 && c + e != row && v[e] > m) m = v[e];
+            if (e4[e] < kInfI32 && c + e != row && e4[e] > m) m = e4[e];
     }
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = (uint32_t)__shfl_xor((int)m, off);
