@@ -6,6 +6,9 @@ round width 128) and checks sampled rows of the state they leave against the
 host oracle: after rounds 0..R-1 the matrix is the Floyd-Warshall state after
 pivots 0..128R-1, whose rows the oracle builds from the adjacency lists.
 """
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -53,3 +56,57 @@ def test_stretch_262144_first_rounds(hubs):
     if hubs:
         assert fin.mean() > 0.99
     assert rel.max() <= REL_TOL
+
+
+@pytest.mark.skipif(not os.environ.get("APSP_FULL_262144"),
+                    reason="a whole n = 262144 solve takes about 9 minutes; "
+                           "set APSP_FULL_262144=1 to run it")
+def test_stretch_262144_full_solve():
+    """The whole n = 262144 Swiss-roll kNN solve (2048 rounds of width 128, in
+    round pairs), run as 32 slices of 64 rounds (bit-identical to one call) so
+    that every slice reports its time.  Sixteen rows and the matching columns
+    (the graph is undirected) are checked against fp64 Dijkstra."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    need = N * N * 4
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} free")
+    import paper_1902_04446_amd as apsp
+
+    u, v, w = gg.swiss_roll_knn(N, gg.CFG_SWISS_256K, 0)
+    D = gg.device_dense_from_edges(N, u, v, w, np.float32, "cuda:0")
+    torch.cuda.synchronize()
+    q = -(-N // apsp.round_width(N))
+    step = 64
+    total = 0.0
+    for r0 in range(0, q, step):
+        t0 = time.perf_counter()
+        apsp.solve_rounds(D, r0, min(q, r0 + step))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        total += dt
+        print(f"n={N}: rounds {r0}..{min(q, r0 + step) - 1} {dt:.2f} s "
+              f"({dt / step * 1e3:.1f} ms per round), {total:.1f} s so far", flush=True)
+    print(f"n={N}: whole solve {total:.1f} s, "
+          f"{float(N) ** 3 / total / 1e12:.2f} T cell-updates/s", flush=True)
+    rng = gg.rng_for(gg.CFG_TEST, N)
+    src = np.concatenate([[0, N - 1], rng.choice(np.arange(1, N - 1), size=14, replace=False)])
+    tsrc = torch.as_tensor(src, device=D.device)
+    rows = D[tsrc].cpu().numpy().astype(np.float64)
+    cols = D[:, tsrc].cpu().numpy().T.astype(np.float64)
+    del D, tsrc
+    torch.cuda.empty_cache()
+    ref = oracle.dijkstra(gg.csr_from_edges(N, u, v, w), N, src, threads=16)
+    worst = 0.0
+    for got in (rows, cols):
+        fin = np.isfinite(ref)
+        assert np.array_equal(fin, np.isfinite(got)), "reachability differs"
+        assert (got[np.arange(src.size), src] == 0).all()
+        rel = np.abs(got[fin] - ref[fin]) / np.maximum(ref[fin], 1e-300)
+        worst = max(worst, float(rel.max(initial=0.0)))
+    print(f"n={N}: {src.size} rows and columns, {int(np.isfinite(ref).sum())} finite entries "
+          f"each way, max rel err vs fp64 Dijkstra {worst:.3e}", flush=True)
+    assert worst <= REL_TOL
