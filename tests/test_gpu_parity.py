@@ -280,6 +280,13 @@ def test_full_size_swiss_16384(apsp, dev):
           f"Bellman residual {bell:.3e}")
 
 
+def test_full_size_swiss_ragged_16461(apsp, dev):
+    """n = 16461 = 128 * 128 + 77 fp32: 64 round pairs, then the partial last
+    round alone."""
+    worst, _ = _full_size_swiss(apsp, dev, 16461, gg.CFG_TEST, 16)
+    print(f"n=16461 fp32: max rel err vs fp64 Dijkstra on sampled rows {worst:.3e}")
+
+
 @pytest.mark.slow
 def test_full_size_swiss_65536(apsp, dev):
     worst, _ = _full_size_swiss(apsp, dev, 65536, gg.CFG_SWISS_64K, 16)
@@ -349,14 +356,22 @@ def test_banded_ragged_int32_rows(apsp, dev, whi, pairs):
         apsp.set_round_pair_threshold(prev)
 
 
-def _banded_ragged(apsp, dev, whi):
+@pytest.mark.parametrize("whi", [100, 1 << 20])
+def test_full_size_ragged_int32(apsp, dev, whi):
+    """n = 16461 = 128 * 128 + 77, int32, at the default pair threshold: 129
+    rounds, i.e. 64 round pairs then the last (partial) round alone, phase 3
+    in two bands; U{1..100} takes the fp32 pipe, U{1..2^20} uint32.  Same
+    checks as at n = 8300."""
+    _banded_ragged(apsp, dev, whi, n=16461, rounds=129)
+
+
+def _banded_ragged(apsp, dev, whi, n=8300, rounds=65):
     import torch
 
-    n = 8300
-    rng = gg.rng_for(gg.CFG_TEST, 1600 + whi)
+    rng = gg.rng_for(gg.CFG_TEST, 1600 + whi + (n != 8300) * n)
     u, v, w = gg.er_edges(n, 6.0 / n, 1, whi, rng)
     D = gg.device_dense_from_edges(n, u, v, w, np.int32, dev)
-    assert apsp.num_rounds(n) == 65
+    assert apsp.num_rounds(n) == rounds
     apsp.solve(D)
     torch.cuda.synchronize()
     csr = gg.csr_from_edges(n, u, v, w)
