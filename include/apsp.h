@@ -104,8 +104,9 @@ int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *strea
  * default 72: measured on MI355X, pairs lose 6% at 64 rounds, where the
  * pair's longer chain of launches on the caller's stream is not hidden, and
  * win 2% at 72 and 7% at 128).  The results are the same either way.
- * rounds >= 2; a value above any q disables pairs.  Process-wide, takes
- * effect for solves enqueued afterwards; no HIP call.
+ * rounds >= 2; pairs need at least 3 rounds whatever the threshold (with
+ * 2 there is no rest set to pair); a value above any q disables pairs.
+ * Process-wide, takes effect for solves enqueued afterwards; no HIP call.
  * Returns the previous threshold, or -1 (unchanged) when rounds < 2.
  */
 int32_t apsp_set_round_pair_threshold(int32_t rounds);

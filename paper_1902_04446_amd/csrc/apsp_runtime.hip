@@ -196,7 +196,10 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     const uint32_t *wmax = dtype == 0 ? h->word : nullptr;
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
-    const bool pairs = q >= g_pair_rounds.load() && r1 - r0 >= 2 && ensure_copies(h, n, s);
+    // Pairs run on the helper streams, which exist from 3 rounds on (below
+    // that a pair has no rest set anyway), whatever the threshold.
+    const bool pairs =
+        lookahead && q >= g_pair_rounds.load() && r1 - r0 >= 2 && ensure_copies(h, n, s);
 
     // Timing: spans of enqueued work on a stream, by category (the PhaseTimes
     // index: 1 phase 1, 2 phase 2, 7 phase 3 on the caller's stream, 5 the

@@ -493,6 +493,34 @@ def test_pair_schedule_random_slices(apsp, dev, pairs_from_8):
             assert np.array_equal(got, oracle.blocked(W, 128)), (n, cuts)
 
 
+@pytest.mark.parametrize("n", [129, 256, 300, 384])
+def test_pair_threshold_two_small_matrices(apsp, dev, n):
+    """Threshold 2 on matrices of 2 and 3 rounds, int32 and fp32, in one call
+    and in calls of two rounds.  Pairs need the helper streams, which fp32
+    matrices of 2 rounds do not get: those run single rounds (a pair would
+    have no rest set), 3 rounds run a pair and the last round alone.
+    Results equal the oracle (int32) and the blocked model (fp32)."""
+    import torch
+
+    prev = apsp.set_round_pair_threshold(2)
+    try:
+        for W in (_er(n, 8.0 / n, 700 + n)[0], _swiss(n, 700 + n)[0]):
+            want = (oracle.fw(W, threads=4) if W.dtype == np.int32 else oracle.blocked(W, 128))
+            q = apsp.num_rounds(n)
+            for cuts in ([0, q], sorted({0, min(2, q), q})):
+                view, _ = _to_dev(W, dev)
+                for a, b in zip(cuts[:-1], cuts[1:]):
+                    apsp.solve_rounds(view, a, b)
+                torch.cuda.synchronize()
+                got = view.cpu().numpy()
+                if W.dtype == np.int32:
+                    assert np.array_equal(got.astype(np.int64), want), (n, cuts)
+                else:
+                    assert np.array_equal(got, want), (n, cuts)
+    finally:
+        apsp.set_round_pair_threshold(prev)
+
+
 def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
     """The profiled solve runs the same schedule (one rest launch group per
     pair of rounds) and gives the same result as single rounds."""

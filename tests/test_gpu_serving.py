@@ -66,6 +66,33 @@ def test_mix_equals_alone(apsp, slice_rounds):
             assert np.array_equal(r.result.cpu().numpy(), oracle.blocked(W, 128))
 
 
+@pytest.mark.parametrize("slice_rounds", [3, 4])
+def test_mix_equals_alone_round_pairs(apsp, slice_rounds):
+    """The same kind of mix with round pairs from 2 rounds on: each slice of
+    3 or 4 rounds runs as pairs (a 3-round slice ends with a round alone),
+    q from 2 to 16, on 3 slot streams at once, each stream with its own panel
+    copies.  Every result equals the single-round solve of the request alone."""
+    import torch
+
+    from paper_1902_04446_amd.serving import ApspServer, GpuBackend
+
+    dev = torch.device("cuda:0")
+    sizes = [1024, 129, 300, 2048, 700, 256, 1100, 513, 1024]
+    reqs = _requests(sizes, 850 + slice_rounds)
+    backend = GpuBackend(dev, slots=3, keep_results=True)
+    srv = ApspServer(backend, hbm_budget=1 << 30, slots=3, slice_rounds=slice_rounds)
+    prev = apsp.set_round_pair_threshold(2)
+    try:
+        stats = srv.run(reqs, realtime=False)
+        torch.cuda.synchronize()
+    finally:
+        apsp.set_round_pair_threshold(prev)
+    assert stats["done"] == len(sizes)
+    for r in reqs:
+        assert r.status == "done"
+        assert torch.equal(r.result, _alone(apsp, r, dev)), r.n
+
+
 def test_admission_under_small_budget(apsp):
     import torch
 

@@ -103,7 +103,7 @@ def _pending(i, j, prev):
     return prev >= 0 and (i == prev or j == prev) and i != prev + 1 and j != prev + 1
 
 
-@pytest.mark.parametrize("q", [8, 9, 10, 13, 17, 33])
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 6, 7, 8, 9, 10, 13, 17, 33])
 def test_pair_tile_maps(q):
     for r in range(q - 1):
         S = {r, r + 1}
@@ -349,7 +349,9 @@ def _pair_schedule(m, q, r0, r1, bands):
         fix(prev, True)
 
 
-@pytest.mark.parametrize("q,r0,r1", [(8, 0, 8), (9, 0, 9), (10, 0, 7), (10, 3, 10), (11, 1, 11),
+@pytest.mark.parametrize("q,r0,r1", [(2, 0, 2), (3, 0, 3), (3, 1, 3), (4, 0, 4), (5, 0, 5),
+                                     (5, 2, 5), (6, 0, 6), (7, 1, 7),
+                                     (8, 0, 8), (9, 0, 9), (10, 0, 7), (10, 3, 10), (11, 1, 11),
                                      (12, 2, 4), (13, 0, 13), (12, 5, 12)])
 @pytest.mark.parametrize("bands", [1, 2, 3])
 def test_pair_schedule_model_is_bit_exact(q, r0, r1, bands):
