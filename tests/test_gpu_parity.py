@@ -521,6 +521,46 @@ def test_pair_threshold_two_small_matrices(apsp, dev, n):
         apsp.set_round_pair_threshold(prev)
 
 
+@pytest.mark.parametrize("shared_stream", [True, False])
+def test_host_threads(apsp, dev, pairs_from_8, shared_stream):
+    """Six host threads solve at once (round pairs, 7 to 17 rounds), all on one
+    stream (the library serialises them on its helper for that stream and
+    grows the panel copies between them) or each on a stream of its own
+    (separate helpers).  Every result equals the same solve run alone."""
+    import threading
+
+    import torch
+
+    sizes = [1100, 2100, 1300, 900, 2100, 1100]
+    mats = [(_swiss(n, 900 + i)[0] if i % 2 else _er(n, 6.0 / n, 900 + i, 1, 1 << 20)[0])
+            for i, n in enumerate(sizes)]
+    want = [_solve(apsp, W, dev) for W in mats]
+    shared = torch.cuda.Stream()
+    got = [None] * len(mats)
+    errors = []
+
+    def work(i):
+        try:
+            st = shared if shared_stream else torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                view, _ = _to_dev(mats[i], dev)
+                apsp.solve(view)
+                out = view.cpu()  # stream-ordered after the solve
+            got[i] = out.numpy()
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(mats))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i, W in enumerate(mats):
+        assert np.array_equal(got[i], want[i]), (i, sizes[i])
+
+
 def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
     """The profiled solve runs the same schedule (one rest launch group per
     pair of rounds) and gives the same result as single rounds."""
