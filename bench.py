@@ -12,8 +12,10 @@ bracketed by device synchronisation.
 
 Besides the headline line, the JSON carries
   roofline     the phase-3 kernel (min-plus tile update, ~98% of the work):
-               algorithmic cell updates / its event-timed duration, against the
-               VALU ceiling for this instruction mix (see ``VALU_PEAK_UPD``);
+               algorithmic cell updates / its event-timed duration, as fp32
+               operations (an add and a min per update) against MI355X's
+               published fp32 vector peak (see ``FP32_PEAK_FLOPS``), with the
+               instruction set's and the measured instruction mix's ceilings;
   cpu_baseline the host oracle (plain Floyd-Warshall in fp64, all host cores)
                timed on a bounded sample of the same workload: the first
                pivots of the n = 16384 problem, scaled by n / pivots (every
@@ -32,18 +34,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU ceiling of MI355X for the min-plus update, from unit counts and clock:
-# 256 CUs at 2.4 GHz issue 128 fp32 lanes per clock each (the 157.3 TFLOP/s
-# fp32 vector figure is 256 x 128 lanes x 2 flops x 2.4e9).  The update costs
-# 1.5 VALU instructions (2 adds + 1 three-input min per 2 updates); at one
-# lane-instruction per lane-slot that is 128 / 1.5 updates per clock per CU.
-# (v_min3 alone issues at half the add rate, but interleaved with the adds the
-# mix gets close to this bound: the probe's update_mix figure.)
+# Peak of the VALU for this arithmetic, from MI355X's unit counts and clock:
+# 256 CUs x 2.4 GHz x 128 fp32 lanes per clock x 2 flops (a fused multiply-add)
+# = 157.3 TFLOP/s, the published fp32 vector figure.  A min-plus cell update is
+# two fp32 operations, an add and a min (no multiply-add: it cannot fuse), so
+# against that figure an update counts 2 ops and the peak is 78.6 T updates/s.
+# Two ceilings below it bound what this instruction set can reach:
+#   ISA_FRAC    updates take 1.5 lane-instructions (c = min3(c, a0+b0, a1+b1)
+#               folds two updates into 2 adds + 1 min3), 4 ops per 3 lane-slots
+#               against the 2 ops per lane-slot of an FMA: 2/3 of the peak;
+#   the measured register-only update mix (VALU probe, reported live): about
+#               0.58 of the peak, since the 3-operand min3 issues at half the
+#               add's lane rate.
 CUS, CLOCK_HZ = 256, 2.4e9
-LANES_PER_CLK = 128
-VALU_INSTR_PER_UPDATE = 1.5
-UPDATES_PER_CLK_PER_CU = LANES_PER_CLK / VALU_INSTR_PER_UPDATE
-VALU_PEAK_UPD = CUS * CLOCK_HZ * UPDATES_PER_CLK_PER_CU   # 52.43e12 updates/s
+FP32_LANES_PER_CLK = 128
+FP32_PEAK_FLOPS = CUS * CLOCK_HZ * FP32_LANES_PER_CLK * 2   # 157.3e12
+OPS_PER_UPDATE = 2                                          # one add, one min
+PEAK_UPD = FP32_PEAK_FLOPS / OPS_PER_UPDATE                 # 78.6e12 updates/s
+ISA_FRAC = (4 / 3) / 2                                      # 0.667 of the peak
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
@@ -145,8 +153,24 @@ def phase3_traffic() -> float | None:
     return float(kv["bytes_per_launch"])
 
 
+def cpu_model() -> str | None:
+    """The host CPU's model name (as lscpu prints it, from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
-    """Time the host oracle on the first pivots of the same workload."""
+    """Time the host oracle on pivots of the same workload, on all host threads
+    (``target_s`` of work) and on one thread (a quarter of it).
+
+    Every pivot step of the plain Floyd-Warshall loop does the same n^2 updates
+    whatever the data (it is branch-free), so the rate over k pivots is the
+    rate of the whole solve, which is projected as n / k times the sample."""
     import numpy as np
 
     import graphgen as gg
@@ -156,19 +180,30 @@ def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
     W = gg.dense_from_edges(n, u, v, w, np.float32)
     D = oracle.prepare(W)
     del W
-    t0 = time.perf_counter()
-    oracle.fw_steps(D, 0, 8, threads=threads)
-    dt = time.perf_counter() - t0
-    k = int(max(8, min(n - 8, target_s / max(dt / 8, 1e-9))))
-    log(f"cpu baseline: 8 pivots in {dt:.2f}s; timing {k} more pivots on {threads} threads")
-    t0 = time.perf_counter()
-    oracle.fw_steps(D, 8, 8 + k, threads=threads)
-    dt = time.perf_counter() - t0
-    rate = k * float(n) ** 2 / dt  # cell updates per second
+
+    def sample(k0: int, budget: float, nthreads: int):
+        t0 = time.perf_counter()
+        oracle.fw_steps(D, k0, k0 + 2, threads=nthreads)
+        per = (time.perf_counter() - t0) / 2
+        k = int(max(2, min(n - k0 - 2, budget / max(per, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.fw_steps(D, k0 + 2, k0 + 2 + k, threads=nthreads)
+        dt = time.perf_counter() - t0
+        return k0 + 2, k, dt, k * float(n) ** 2 / dt
+
+    k0, k, dt, rate = sample(0, target_s, threads)
+    log(f"cpu baseline: {k} pivots on {threads} threads in {dt:.1f} s")
+    k1_0, k1, dt1, rate1 = sample(k0 + k, target_s / 4, 1)
+    log(f"cpu baseline: {k1} pivots on 1 thread in {dt1:.1f} s")
     return {"value": rate / 1e9, "unit": "G cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"pivots 8..{8 + k - 1} of the n={n} fp64 Floyd-Warshall loop "
-                      f"({k} of {n} pivots, {dt:.1f} s); full solve projected at "
-                      f"{n / k * dt:.0f} s"}
+            "sample": f"pivots {k0}..{k0 + k - 1} of the n={n} fp64 Floyd-Warshall loop on "
+                      f"{threads} threads ({k} of {n} pivots, {dt:.1f} s); every pivot step "
+                      f"costs the same, so the full solve projects to {n / k * dt:.0f} s",
+            "single_thread": {"value": rate1 / 1e9, "unit": "G cell-updates/s", "cores": 1,
+                              "sample": f"pivots {k1_0}..{k1_0 + k1 - 1} ({k1} pivots, "
+                                        f"{dt1:.1f} s); full solve projects to "
+                                        f"{n / k1 * dt1:.0f} s"},
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
 
 
 def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True) -> dict:
@@ -292,7 +327,7 @@ def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2)) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in probe:
-        D = backend.alloc(r)
+        D = backend.alloc(r, 0)
         backend.load(D, r, 0)
         with torch.cuda.stream(backend.streams[0]):
             apsp.solve(D)
@@ -527,11 +562,14 @@ def rest_roofline(phases: dict, K: int, n: int, b: int) -> dict:
     return {
         "bound": "alu",
         "kernel": kernel,
-        "achieved": round(achieved / 1e12, 3),
-        "peak": round(VALU_PEAK_UPD / 1e12, 3),
-        "unit": "T cell-updates/s",
-        "frac": round(achieved / VALU_PEAK_UPD, 4),
+        "achieved": round(achieved * OPS_PER_UPDATE / 1e12, 3),
+        "peak": round(FP32_PEAK_FLOPS / 1e12, 2),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_UPD, 4),
         "traffic": None,
+        "ops_per_update": OPS_PER_UPDATE,
+        "achieved_T_cell_updates_per_s": round(achieved / 1e12, 3),
+        "ceiling_isa_frac": round(ISA_FRAC, 4),
         "per_launch_updates": round(per_launch),
         "avg_launch_ms": round(launch_s * 1e3, 4),
     }
@@ -645,6 +683,12 @@ def main() -> int:
     q = -(-n // b)
     roofline = rest_roofline(phases, K, n, b)
     roofline["traffic"] = phase3_traffic() if n == 16384 else None
+    roofline["solve_frac"] = round(value / PEAK_UPD, 4)
+    if probe and probe.get("update_mix_T_updates_per_s"):
+        mix = probe["update_mix_T_updates_per_s"] * 1e12
+        roofline["ceiling_mix_frac"] = round(mix / PEAK_UPD, 4)
+        roofline["frac_of_mix_ceiling"] = round(
+            roofline["achieved_T_cell_updates_per_s"] * 1e12 / mix, 4)
 
     variants = None
     if args.variants:

@@ -115,17 +115,33 @@ def _dtype_code(t) -> int:
     raise TypeError(f"APSP matrices are int32 or float32, got {t.dtype}")
 
 
+def _row_stride(shape, stride, what="matrix") -> int:
+    """Leading dimension of a 2-D view with unit column stride: ``stride[0]``,
+    which must be at least the row length so that rows do not overlap (a
+    broadcast or overlapping ``as_strided`` view would make the library write
+    one element through several indices).  Single-row views have no row
+    stride to check; they report max(stride[0], cols, 1)."""
+    rows, cols = int(shape[0]), int(shape[1])
+    if cols > 1 and stride[1] != 1:
+        raise ValueError(f"{what} columns must be contiguous (stride(1) == 1)")
+    if rows > 1:
+        if stride[0] < max(cols, 1):
+            raise ValueError(f"{what} rows overlap: stride(0) = {stride[0]} < {cols} columns "
+                             "(broadcast or overlapping view)")
+        return int(stride[0])
+    return max(int(stride[0]), cols, 1)
+
+
 def _matrix_args(t):
     """(pointer, n, ld, dtype) of a square device matrix view with unit column stride."""
-    if not t.is_cuda:
-        raise ValueError("the APSP library works on device (ROCm) tensors only")
     if t.dim() != 2 or t.shape[0] != t.shape[1]:
         raise ValueError(f"expected a square 2-D matrix, got shape {tuple(t.shape)}")
     n = int(t.shape[0])
-    if n > 1 and t.stride(1) != 1:
-        raise ValueError("matrix columns must be contiguous (stride(1) == 1)")
-    ld = int(t.stride(0)) if n > 1 else max(1, int(t.stride(0)))
-    return t.data_ptr(), n, max(ld, n, 1), _dtype_code(t)
+    ld = _row_stride(t.shape, t.stride())
+    dt = _dtype_code(t)
+    if not t.is_cuda:
+        raise ValueError("the APSP library works on device (ROCm) tensors only")
+    return t.data_ptr(), n, ld, dt
 
 
 def _stream(stream):
@@ -218,23 +234,20 @@ def _batch_arrays(mats):
     dt = _dtype_code(mats[0])
     dev = mats[0].device
     tdt = mats[0].dtype
-    if not mats[0].is_cuda:
-        raise ValueError("the APSP library works on device (ROCm) tensors only")
     for g, m in enumerate(mats):
         if m.dtype != tdt:
             raise TypeError("a batch must have a single dtype")
-        if m.device != dev:
-            raise ValueError("all matrices of a batch must be on one device")
         shp = m.shape
         if len(shp) != 2 or shp[0] != shp[1]:
             raise ValueError(f"expected square 2-D matrices, got shape {tuple(shp)}")
-        n = shp[0]
-        st = m.stride()
-        if n > 1 and st[1] != 1:
-            raise ValueError("matrix columns must be contiguous (stride(1) == 1)")
+        lds[g] = _row_stride(shp, m.stride(), f"matrix {g}")
+    if not mats[0].is_cuda:
+        raise ValueError("the APSP library works on device (ROCm) tensors only")
+    for g, m in enumerate(mats):
+        if m.device != dev:
+            raise ValueError("all matrices of a batch must be on one device")
         ptrs[g] = m.data_ptr()
-        ns[g] = n
-        lds[g] = max(st[0], n, 1)
+        ns[g] = int(m.shape[0])
     del torch
     return ptrs, ns, lds, dt, dev
 
@@ -352,9 +365,11 @@ class _nullcontext:
 
 def minplus(C, A, B, accumulate: bool = False, stream=None):
     """C = A (x) B (min-plus product), or C = min(C, A (x) B) with accumulate.  In place on C."""
+    lds = {}
     for name, t in (("C", C), ("A", A), ("B", B)):
-        if not t.is_cuda or t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
-            raise ValueError(f"{name} must be a 2-D device matrix with contiguous rows")
+        if t.dim() != 2:
+            raise ValueError(f"{name} must be a 2-D matrix")
+        lds[name] = _row_stride(t.shape, t.stride(), name)
     if not (C.dtype == A.dtype == B.dtype):
         raise TypeError("C, A and B must have one dtype")
     m, k = A.shape
@@ -362,10 +377,13 @@ def minplus(C, A, B, accumulate: bool = False, stream=None):
     if k != k2 or tuple(C.shape) != (m, n):
         raise ValueError(f"shape mismatch: C {tuple(C.shape)}, A {tuple(A.shape)}, B {tuple(B.shape)}")
     dt = _dtype_code(C)
-    ld = lambda t: max(int(t.stride(0)), int(t.shape[1]), 1)  # noqa: E731
+    for name, t in (("C", C), ("A", A), ("B", B)):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device (ROCm) matrix")
     with _device_of(C):
-        _check(_LIB.apsp_minplus(ctypes.c_void_p(C.data_ptr()), ld(C), ctypes.c_void_p(A.data_ptr()),
-                                 ld(A), ctypes.c_void_p(B.data_ptr()), ld(B), m, n, k, dt,
+        _check(_LIB.apsp_minplus(ctypes.c_void_p(C.data_ptr()), lds["C"],
+                                 ctypes.c_void_p(A.data_ptr()), lds["A"],
+                                 ctypes.c_void_p(B.data_ptr()), lds["B"], m, n, k, dt,
                                  1 if accumulate else 0, _stream(stream)), "apsp_minplus")
     return C
 

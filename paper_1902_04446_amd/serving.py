@@ -83,7 +83,7 @@ class SimBackend:
     def num_rounds(self, n: int) -> int:
         return -(-n // self.b) if n else 0
 
-    def alloc(self, req: Request):
+    def alloc(self, req: Request, slot: int):
         self.allocated += 1
         return {"n": req.n}
 
@@ -140,9 +140,13 @@ class GpuBackend:
     def num_rounds(self, n: int) -> int:
         return self.apsp.num_rounds(n)
 
-    def alloc(self, req: Request):
+    def alloc(self, req: Request, slot: int):
+        # allocated on the slot stream, where every later use of it is ordered:
+        # the caching allocator then only hands out a block whose earlier uses
+        # on that stream precede this request's work
         tdt = self.torch.float32 if self.dtype == "f32" else self.torch.int32
-        return self.torch.empty((req.n, req.n), dtype=tdt, device=self.device)
+        with self.torch.cuda.stream(self.streams[slot]):
+            return self.torch.empty((req.n, req.n), dtype=tdt, device=self.device)
 
     def free(self, handle):
         pass  # dropped with the last reference (torch's caching allocator reuses it)
@@ -298,7 +302,7 @@ class ApspServer:
             if self.used + need <= self.budget and not blocked:
                 self.pending.remove(req)
                 req.slot = self.free_slots.pop(0)
-                req.handle = self.backend.alloc(req)
+                req.handle = self.backend.alloc(req, req.slot)
                 self.used += need
                 req.rounds = self.backend.num_rounds(req.n)
                 req.next_round = 0

@@ -297,3 +297,35 @@ def test_bench_refuses_several_gpus():
                          capture_output=True, text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU" in out.stderr and out.stdout == ""
+
+
+def test_binding_rejects_overlapping_row_views():
+    """A broadcast or overlapping view would make the library write one element
+    through several indices; the binding rejects it before any HIP call (the
+    tensors here are host tensors, so a HIP call would fail differently)."""
+    import torch
+
+    import paper_1902_04446_amd as apsp
+
+    bad = [torch.full((5,), 1.0).expand(5, 5),
+           torch.zeros(40, dtype=torch.int32).as_strided((5, 5), (3, 1)),
+           torch.zeros(40).as_strided((5, 5), (0, 1))]
+    for t in bad:
+        with pytest.raises(ValueError, match="rows overlap"):
+            apsp._matrix_args(t)
+        with pytest.raises(ValueError, match="rows overlap"):
+            apsp.solve(t)
+        with pytest.raises(ValueError, match="rows overlap"):
+            apsp._batch_arrays([torch.zeros((3, 3), dtype=t.dtype), t])
+        with pytest.raises(ValueError, match="rows overlap"):
+            apsp.minplus(torch.zeros((5, 5), dtype=t.dtype), t, torch.zeros((5, 5), dtype=t.dtype))
+    # non-unit column stride (a transposed view)
+    with pytest.raises(ValueError, match="contiguous"):
+        apsp._matrix_args(torch.zeros((4, 4)).t()[:, :3][:3])
+    # padded rows are fine (the check reaches the device test only)
+    padded = torch.zeros((4, 7))[:, :4]
+    with pytest.raises(ValueError, match="device"):
+        apsp._matrix_args(padded)
+    # single rows: no row stride to check
+    with pytest.raises(ValueError, match="device"):
+        apsp._matrix_args(torch.zeros((1, 1)))

@@ -900,19 +900,92 @@ def test_minplus_rejects_overlap(apsp, dev):
 # ------------------------------------------------------------ symmetric variant
 
 @pytest.mark.parametrize("n", [1, 2, 100, 129, 300, 700, 1000])
-def test_symmetric_variant_equals_full_solve(apsp, dev, n):
-    """Upper-triangle solve of an undirected graph: same bits as the full solve;
-    the input's lower triangle is never read."""
+def test_symmetric_variant_vs_oracle(apsp, dev, n):
+    """Upper-triangle solve of an undirected graph (Sec. 4 storage) against the
+    oracle: int32 equals Floyd-Warshall exactly; fp32 equals the oracle's
+    blocked fp32 model at width 128 bit for bit and lies within 1e-5 of fp64
+    Floyd-Warshall.  The input's lower triangle holds junk and its diagonal
+    nonzero values: the variant must read neither."""
     import torch
 
     Wi, _ = _er(n, min(1.0, 4.0 / n), 9500 + n)
     Wf, _ = _swiss(n, 9600 + n) if n > 11 else (np.zeros((n, n), np.float32), None)
     for W in (Wi, Wf):
-        full = _solve(apsp, W, dev)
         junk = W.copy()
         low = np.tril_indices(n, -1)
-        junk[low] = 3 if W.dtype == np.int32 else np.float32(0.125)
-        view, _ = _to_dev(junk, dev, ld=n + 4)
+        if W.dtype == np.int32:
+            junk[low] = 3
+            np.fill_diagonal(junk, 7)
+        else:
+            junk[low] = np.float32(0.125)
+            np.fill_diagonal(junk, np.float32(2.5e3))
+        view, buf = _to_dev(junk, dev, ld=n + 4)
+        before = buf.clone()
         apsp.solve_symmetric(view)
         torch.cuda.synchronize()
-        assert np.array_equal(view.cpu().numpy(), full), (n, W.dtype)
+        got = view.cpu().numpy()
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W)), n
+        else:
+            assert np.array_equal(got, oracle.blocked(W, 128)), n
+            _assert_f32_close(got, oracle.fw(W))
+        # nothing outside the n x n view was written
+        mask = torch.ones_like(buf, dtype=torch.bool)
+        mask[:n * (n + 4)].view(n, n + 4)[:, :n] = False
+        assert torch.equal(buf[mask], before[mask])
+
+
+# ------------------------------------------------- fp32 input with a diagonal
+
+def _f32_with_diagonal(n, seed):
+    """Swiss-roll kNN matrix whose diagonal holds nonzero weights, some huge
+    (3e38) and some +inf: the empty path must still give D_ii = 0."""
+    W, _ = _swiss(n, seed) if n > 11 else (np.zeros((n, n), np.float32), None)
+    rng = gg.rng_for(gg.CFG_TEST, seed + 1)
+    d = (rng.random(n) * 5 + 0.5).astype(np.float32)
+    d[::3] = np.float32(3e38)
+    d[1::3] = np.inf
+    W = W.copy()
+    np.fill_diagonal(W, d)
+    return W
+
+
+@pytest.mark.parametrize("n", [1, 2, 129, 300, 513])
+def test_fp32_nonzero_diagonal(apsp, dev, n):
+    """fp32 inputs with a nonzero diagonal through every fp32 entry point, each
+    against the oracle (which takes the diagonal as the empty path)."""
+    import torch
+
+    W = _f32_with_diagonal(n, 9700 + n)
+    ref = oracle.blocked(W, 128)
+    ref64 = oracle.fw(W)
+    assert (np.diag(ref) == 0).all()
+    # apsp_solve
+    got = _solve(apsp, W, dev)
+    assert np.array_equal(got, ref), "apsp_solve"
+    _assert_f32_close(got, ref64)
+    # apsp_solve_rounds from round 0, in two slices
+    q = apsp.num_rounds(n)
+    view, _ = _to_dev(W, dev)
+    apsp.solve_rounds(view, 0, 1)
+    apsp.solve_rounds(view, 1, q)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy(), ref), "apsp_solve_rounds"
+    # apsp_solve_symmetric (W is symmetric off the diagonal)
+    view, _ = _to_dev(W, dev, ld=n + 2)
+    apsp.solve_symmetric(view)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy(), ref), "apsp_solve_symmetric"
+    # batched, one-shot call and both forced widths
+    views = [_to_dev(W, dev)[0] for _ in range(3)]
+    apsp.solve_batched([views[0]])
+    plans = [apsp.BatchPlan([views[1]], tile=64), apsp.BatchPlan([views[2]], tile=128)]
+    for p in plans:
+        p.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(views[0].cpu().numpy(),
+                          oracle.blocked(W, apsp.batched_round_width(n, apsp.APSP_F32)))
+    assert np.array_equal(views[1].cpu().numpy(), oracle.blocked(W, 64)), "batched width 64"
+    assert np.array_equal(views[2].cpu().numpy(), ref), "batched width 128"
+    for p in plans:
+        p.close()
