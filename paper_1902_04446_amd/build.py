@@ -32,16 +32,35 @@ FLAGS = [
 ]
 
 
-def _compile(sources, out, extra, verbose):
-    srcs = [os.path.join(CSRC, s) for s in sources]
-    tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, *srcs, "-o", tmp]
+def _run(cmd, verbose, what):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+        raise RuntimeError(f"hipcc failed building {what}")
+
+
+def _compile(sources, out, extra, verbose):
+    """Compile each source to an object in parallel (each translation unit
+    launches only its own kernels), then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    flags = [f for f in FLAGS if f != "-shared"]
+    objs = []
+    jobs = []
+    for src in sources:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        objs.append(obj)
+        jobs.append(([HIPCC, *flags, *extra, "-c", os.path.join(CSRC, src), "-o", obj], src))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose, what) for cmd, what in jobs]:
+            f.result()
+    tmp = out + ".tmp"
+    _run([HIPCC, *FLAGS, *extra, *objs, "-o", tmp], verbose, os.path.basename(out))
     os.replace(tmp, out)
     return out
 

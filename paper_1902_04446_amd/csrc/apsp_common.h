@@ -143,34 +143,56 @@ int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 int64_t num_rounds(int64_t n);
 
 // ---- round pairs (apsp_pair.hip) -------------------------------------------
-// Copies of round pr's block row and block column, written by phase 2 of the
-// second round of a pair; three slots.  row[s]: 128 x ld (row k of the block
-// row at offset k*ld); col[s]: q*128 x 128 (the block column's row i at
-// offset i*128).
+// Copies of round panels, all with leading dimension ld = 128 q (q rounds):
+// row[s] holds a block row (its row k at offset k * ld); colT[s] a block
+// column stored transposed (the block's column k at offset k * ld, matrix row
+// i at position i), the layout the direct-staged rest pass takes its A operand
+// in.  Phase 2 of a pair's second round writes row[s] and colT[s] for s in a
+// three-slot ring (a pass may still read the previous pair's copies while the
+// next pair writes its own); phase 2 of a pair's first round writes colT[3]
+// or colT[4], alternating between pairs.
+constexpr int kPairRowSlots = 3;
+constexpr int kPairFirstSlot0 = 3;  // colT slots 3, 4: the pair's first round
 struct PairCopies {
-    uint32_t *row[3] = {};
-    uint32_t *col[3] = {};
+    uint32_t *row[kPairRowSlots] = {};
+    uint32_t *colT[5] = {};
     int64_t ld = 0;
 };
 // Blocks r+2, r+3 that exist (0..2): the next pair's.
 int pair_next_blocks(int64_t n, int64_t r);
-// Phase 2 of round pr, also written to copy slot `slot`.
+// Phase 2 of round pr, also written to the copies: block row to row[row_slot]
+// (none when row_slot < 0), block column transposed to colT[col_slot].
 hipError_t launch_pair_panels(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t pr,
-                              const PairCopies &c, int slot, hipStream_t s,
+                              const PairCopies &c, int row_slot, int col_slot, hipStream_t s,
                               const uint32_t *wmax);
+// Round r's phase 3 on block row/column r+1 (the tiles round r+1 reads
+// first), closing diagonal block r+1 after its update: launch_tile_set(kNext)
+// with the fused closure, or its direct-staged form (as launch_pair_rest),
+// the column panel of round r read from colT[first_slot].
+hipError_t launch_pair_round_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                                  const PairCopies &c, int first_slot, hipStream_t s,
+                                  const uint32_t *wmax);
 // Phase 3 of rounds r and r+1 on the tiles of block rows/columns r+2, r+3
 // outside blocks r, r+1; `close` closes diagonal block r+2 after its update.
 // prev >= 0: tiles of block row/column prev (but prev+1) first take round
-// prev+1's deferred update from copy slot prev_slot.
+// prev+1's deferred update from copy slot prev_slot (row and colT).  The
+// column panels of rounds r and r+1 are in colT[first_slot] and colT[slot]
+// (read by the direct-staged kernel; see launch_pair_rest).
 hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
                             bool close, int64_t prev, const PairCopies &c, int prev_slot,
-                            hipStream_t s, const uint32_t *wmax);
+                            int first_slot, int slot, hipStream_t s, const uint32_t *wmax);
 // Phase 3 of rounds r and r+1 on the tiles outside blocks r .. r+1+next
-// whose block row is in [lo, hi); deferred updates as launch_pair_next.
+// whose block row is in [lo, hi); deferred updates as launch_pair_next.  The
+// column panels of rounds r and r+1 are in colT[first_slot] and colT[slot]
+// (read by the direct-staged fp32 kernel, which full tiles of aligned fp32
+// matrices take; the other kernels read them from the matrix).
 hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
                             int64_t lo, int64_t hi, int64_t prev, const PairCopies &c,
-                            int prev_slot, hipStream_t s, const uint32_t *wmax);
+                            int prev_slot, int first_slot, int slot, hipStream_t s,
+                            const uint32_t *wmax);
 int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
+// Whether launch_pair_rest takes the direct-staged kernel for this matrix.
+bool pair_rest_direct(const uint32_t *D, int64_t n, int64_t ld, int dtype);
 // Round r+1's deferred phase-3 update on block row/column r: !final_: tiles
 // (x, r), (r, x) for the next blocks x; final_: every other one but the
 // blocks r+1.

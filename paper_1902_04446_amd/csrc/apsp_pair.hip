@@ -18,12 +18,21 @@
 //   * the other tiles of block row/column r get it at the start of their
 //     update in the next pair's pass, from a copy of round r+1's panels
 //     taken when phase 2 of round r+1 wrote them (by then the next pair may
-//     have changed block row/column r+1 in the matrix itself);
+//     have changed block row/column r+1 in the matrix itself; the column
+//     panel is copied transposed);
 //   * at the end of a call, kFix (final) applies what is left, so a call
 //     always leaves exactly the state of Floyd-Warshall after its last round.
 // The schedule (apsp_runtime.hip) keeps every read of these tiles ahead of
 // every write to them; the result is the same as running the rounds one by
 // one, bit for bit.
+//
+// The rest pass (kRest2, ~98% of the work) has a second form for fp32
+// matrices whose tiles are all full and rows 16-byte aligned: the operands go
+// from memory straight to LDS (tile::minplus_tile_direct), the column panels
+// of rounds r and r+1 read from their transposed copies (phase 2 of each
+// round writes one), the row panels from the matrix.  Fewer registers per
+// thread let 4 workgroups share a CU instead of 3.  It forms the same
+// candidates and minima, so the same bits.
 #include <algorithm>
 
 #include "apsp_tile.h"
@@ -40,6 +49,7 @@ constexpr int kPanelsSnap = 0;  // phase 2 of round pr, also written to the copy
 constexpr int kNext2 = 1;       // pair pass on block rows/columns r+2, r+3 (outside r, r+1)
 constexpr int kRest2 = 2;       // pair pass on a band of block rows, outside blocks [r, r+2+nxt)
 constexpr int kFix = 3;         // round r+1's deferred update of block row/column r tiles
+constexpr int kNextR = 4;       // round r's phase 3 on block row/column r+1 (direct form only)
 
 struct PairArgs {
     uint32_t *D;
@@ -52,10 +62,13 @@ struct PairArgs {
     int lo, hi;  // kRest2: band [lo, hi) of block rows
     int prev;    // kNext2/kRest2: first round of the previous pair, -1 if none
     int final_;  // kFix: 0 = tiles (x, r), (r, x) for next blocks x; 1 = the rest
-    const uint32_t *prow;  // copy of the previous pair's round prev+1 block row
-    const uint32_t *pcol;  // ... and block column (rows of 128, leading dimension 128)
-    int64_t ldc;           // leading dimension of the block-row copies
-    uint32_t *srow, *scol; // kPanelsSnap: copies to write (same layout)
+    const uint32_t *prow;   // copy of the previous pair's round prev+1 block row
+    const uint32_t *pcolT;  // ... and its block column, transposed
+    const uint32_t *at0;    // kRest2 direct: round r's block column, transposed
+    const uint32_t *at1;    // ... and round r+1's
+    int64_t ldc;            // leading dimension of the copies
+    uint32_t *srow;         // kPanelsSnap: block-row copy to write (or null)
+    uint32_t *scolT;        // kPanelsSnap: transposed block-column copy to write
 };
 
 __device__ __forceinline__ int width(int64_t n, int blk) {
@@ -113,6 +126,23 @@ __device__ __forceinline__ Job job_of(const PairArgs &a) {
         j.kblocks = 1;
         return j;
     }
+    if (MODE == kNextR) {
+        // block row r+1 (every column but r), then block column r+1 (every
+        // row but r, r+1): the tiles the next round's phases read; the
+        // workgroup of diagonal block r+1 closes it (phase 1 of round r+1)
+        int t = blockIdx.x;
+        if (t < q - 1) {
+            j.I = r + 1;
+            j.J = t < r ? t : t + 1;
+        } else {
+            t -= q - 1;
+            j.J = r + 1;
+            j.I = t < r ? t : t + 2;
+        }
+        j.kblocks = 1;
+        j.close = a.close && j.I == r + 1 && j.J == r + 1;
+        return j;
+    }
     const int m = q - 2;  // blocks outside r, r+1
     if (MODE == kNext2) {
         // block rows r+2.. (every column outside r, r+1), then block columns
@@ -168,24 +198,104 @@ __device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
     tile::load_acc<Op, NORM, kStream>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
     if (MODE != kPanelsSnap && MODE != kFix && jb.pending)
         // round prev+1 on a tile of block row/column prev, from the copies
-        tile::minplus_tile_ab<Op, NORM>(acc, a.pcol, TB, a.prow, a.ldc, i0, j0, mr, nc,
-                                        width(a.n, a.prev + 1), true, L);
+        // (the column panel's is transposed)
+        tile::minplus_tile_ab<Op, NORM, true, false>(acc, a.pcolT, a.ldc, a.prow, a.ldc, i0, j0,
+                                                     mr, nc, width(a.n, a.prev + 1), true, L);
     tile::minplus_tile<Op, NORM>(acc, a.D, a.ld, i0, j0, kb, mr, nc, kw, vec, L);
     if (MODE == kNext2 && jb.close)  // phase 1 of round r+2, fused
         tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
     tile::store_acc<Op, kStream>(acc, a.D, a.ld, i0, j0, mr, nc, vec);
     if (MODE == kPanelsSnap) {
-        if (jb.I == a.r)  // block row: row k of the copy holds row k of the block
-            tile::store_acc<Op>(acc, a.srow, a.ldc, 0, j0, mr, nc, true);
-        else              // block column: rows of 128, at their matrix row
-            tile::store_acc<Op>(acc, a.scol, TB, i0, 0, mr, nc, true);
+        if (jb.I == a.r) {  // block row: row k of the copy holds row k of the block
+            if (a.srow) tile::store_acc<Op>(acc, a.srow, a.ldc, 0, j0, mr, nc, true);
+        } else {            // block column: column k of the block at row k of the copy
+            tile::store_acc_t<Op>(acc, a.scolT, a.ldc, i0, mr, nc);
+        }
     }
+}
+
+// The rest pass of a pair with direct staging (full tiles of an aligned fp32
+// matrix): the column panels from their transposed copies, the row panels
+// from the matrix.  The output tile is addressed as one uniform base pointer
+// plus 32-bit lane offsets (the caller guarantees 128 ld < 2^30), and the
+// offsets are formed again for the store (the empty asm statements hide that
+// base and ld are unchanged), so no 64-bit row address stays live across the
+// products: that keeps the kernel at 128 registers without spilling.
+__device__ __forceinline__ void tile_io_direct(uint32_t (&acc)[8][8], uint32_t *base, uint32_t ld,
+                                               bool store) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const uint32_t off = (uint32_t)tile::row_of(m, ty) * ld + (uint32_t)tx * 4u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t *p = base + off + h * 64;
+            if (store) {
+                tile::st4_stream(p, make_uint4(acc[m][h * 4 + 0], acc[m][h * 4 + 1],
+                                               acc[m][h * 4 + 2], acc[m][h * 4 + 3]));
+            } else {
+                const uint4 v = tile::ld4_stream(p);
+                acc[m][h * 4 + 0] = v.x;
+                acc[m][h * 4 + 1] = v.y;
+                acc[m][h * 4 + 2] = v.z;
+                acc[m][h * 4 + 3] = v.w;
+            }
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void pair_direct_update(const PairArgs &a, tile::Lds &L) {
+    const Job jb = job_of<MODE>(a);
+    const int64_t i0 = (int64_t)jb.I * TB, j0 = (int64_t)jb.J * TB;
+    uint32_t acc[8][8];
+    tile_io_direct(acc, a.D + i0 * a.ld + j0, (uint32_t)a.ld, false);
+    // product 0: round prev+1's deferred update from the copies (pending
+    // tiles only); product 1: rounds r and r+1.  One call site keeps the
+    // register count at 4 workgroups per CU.
+#pragma unroll 1
+    for (int x = jb.pending ? 0 : 1; x < 2; ++x) {
+        const uint32_t *at0 = x ? a.at0 : a.pcolT, *at1 = x ? a.at1 : a.pcolT;
+        const uint32_t *B = x ? a.D + (int64_t)a.r * TB * a.ld : a.prow;
+        tile::minplus_tile_direct<OpF32>(acc, at0, at1, TB, a.ldc, B, x ? a.ld : a.ldc, i0, j0,
+                                         x ? jb.kblocks * TB : TB, L);
+    }
+    if (MODE != kRest2 && jb.close)  // phase 1 of round r+2 (kNext2) or r+1 (kNextR), fused
+        tile::close_block<OpF32>(acc, TB, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+    uint32_t *base = a.D + i0 * a.ld + j0;
+    uint32_t ld = (uint32_t)a.ld;
+    asm volatile("" : "+s"(base), "+s"(ld));
+    tile_io_direct(acc, base, ld, true);
 }
 
 template <class Op, int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_pair(PairArgs a) {
     __shared__ tile::Lds L;
+    if (MODE != kRest2) tile::chain_priority();
     pair_update<Op, MODE, false>(a, L);
+}
+
+// The rest pass (kRest2) and the pass on block rows/columns r+2, r+3
+// (kNext2, with its closure) in direct-staged form.  The chain launches
+// (kNext2 among them) run beside the previous pair's bands, whose workgroups
+// fill a CU 4 at a time with 120 registers each (480 of 512 per SIMD): a
+// chain workgroup gets a CU as soon as one band workgroup ends only if it
+// needs at most 152, which the other chain kernels do (138-144) but the
+// register-staged kNext2 (154) does not.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rest_direct(
+    PairArgs a) {
+    __shared__ tile::Lds L;
+    pair_direct_update<kRest2>(a, L);
+}
+
+// kNext2 and kNextR (with the closure's registers: at most 152, 3 workgroups
+// per CU)
+template <int MODE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_next_direct(
+    PairArgs a) {
+    __shared__ tile::Lds L;
+    tile::chain_priority();
+    pair_direct_update<MODE>(a, L);
 }
 
 // int32 on the fp32 pipe (OpI32F, bit-identical) when *wmax allows it.
@@ -193,6 +303,7 @@ template <int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_i32(
     PairArgs a, const uint32_t *__restrict__ wmax) {
     __shared__ tile::Lds L;
+    if (MODE != kRest2) tile::chain_priority();
     if (int_exact_in_f32(a.n, *wmax))
         pair_update<OpI32F, MODE, true>(a, L);
     else
@@ -243,32 +354,60 @@ int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
     return rows > 0 ? rows * (q - (e1 - r)) : 0;
 }
 
+bool pair_rest_direct(const uint32_t *D, int64_t n, int64_t ld, int dtype) {
+    return dtype == 1 && n % TB == 0 && (reinterpret_cast<uintptr_t>(D) & 15u) == 0 &&
+           (ld & 3) == 0 && ld < ((int64_t)1 << 23);
+}
+
 hipError_t launch_pair_panels(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t pr,
-                              const PairCopies &c, int slot, hipStream_t s,
+                              const PairCopies &c, int row_slot, int col_slot, hipStream_t s,
                               const uint32_t *wmax) {
     PairArgs a = base_args(D, n, ld, (int)pr, c);
-    a.srow = c.row[slot];
-    a.scol = c.col[slot];
+    a.srow = row_slot >= 0 ? c.row[row_slot] : nullptr;
+    a.scolT = c.colT[col_slot];
     return launch<kPanelsSnap>(a, dtype, wmax, (unsigned)(2 * (a.q - 1)), s);
 }
 
 hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
                             bool close, int64_t prev, const PairCopies &c, int prev_slot,
-                            hipStream_t s, const uint32_t *wmax) {
+                            int first_slot, int slot, hipStream_t s, const uint32_t *wmax) {
     PairArgs a = base_args(D, n, ld, (int)r, c);
     a.close = close ? 1 : 0;
     a.prev = (int)prev;
     if (prev >= 0) {
         a.prow = c.row[prev_slot];
-        a.pcol = c.col[prev_slot];
+        a.pcolT = c.colT[prev_slot];
     }
     const int m = a.q - 2;
-    return launch<kNext2>(a, dtype, wmax, (unsigned)(a.nxt * m + a.nxt * (m - a.nxt)), s);
+    const unsigned count = (unsigned)(a.nxt * m + a.nxt * (m - a.nxt));
+    if (count > 0 && pair_rest_direct(D, n, ld, dtype)) {
+        a.at0 = c.colT[first_slot];
+        a.at1 = c.colT[slot];
+        hipLaunchKernelGGL(k_pair_next_direct<kNext2>, dim3(count), dim3(NT), 0, s, a);
+        return hipGetLastError();
+    }
+    return launch<kNext2>(a, dtype, wmax, count, s);
+}
+
+hipError_t launch_pair_round_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                                  const PairCopies &c, int first_slot, hipStream_t s,
+                                  const uint32_t *wmax) {
+    if (!pair_rest_direct(D, n, ld, dtype))
+        return launch_tile_set(D, n, ld, dtype, r, kNext, s, true, wmax);
+    PairArgs a = base_args(D, n, ld, (int)r, c);
+    if (r + 1 >= a.q) return hipSuccess;
+    a.close = 1;
+    a.at0 = c.colT[first_slot];
+    a.at1 = a.at0;
+    hipLaunchKernelGGL(k_pair_next_direct<kNextR>, dim3((unsigned)(2 * a.q - 3)), dim3(NT), 0, s,
+                       a);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
                             int64_t lo, int64_t hi, int64_t prev, const PairCopies &c,
-                            int prev_slot, hipStream_t s, const uint32_t *wmax) {
+                            int prev_slot, int first_slot, int slot, hipStream_t s,
+                            const uint32_t *wmax) {
     const int64_t count = pair_rest_count(n, r, lo, hi);
     if (count <= 0) return hipSuccess;
     PairArgs a = base_args(D, n, ld, (int)r, c);
@@ -277,7 +416,13 @@ hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
     a.prev = (int)prev;
     if (prev >= 0) {
         a.prow = c.row[prev_slot];
-        a.pcol = c.col[prev_slot];
+        a.pcolT = c.colT[prev_slot];
+    }
+    if (pair_rest_direct(D, n, ld, dtype)) {
+        a.at0 = c.colT[first_slot];
+        a.at1 = c.colT[slot];
+        hipLaunchKernelGGL(k_pair_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
+        return hipGetLastError();
     }
     return launch<kRest2>(a, dtype, wmax, (unsigned)count, s);
 }

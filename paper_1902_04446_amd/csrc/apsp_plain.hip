@@ -83,6 +83,7 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
                                                  int kw) {
     __shared__ __align__(16) uint32_t rowbuf[2][TB];
     __shared__ uint32_t colbuf[2][TB];
+    tile::chain_priority();
     const int t = threadIdx.x;
     const int i = t >> 3;
     const int cg = t & 7;
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
     int row_lo, int row_hi) {
     __shared__ tile::Lds L;
+    if (MODE == kPanels || MODE == kNext) tile::chain_priority();
     int I, J;
     tile_of<MODE>(r, q, row_lo, row_hi, I, J);
     tile_update<Op, MODE, false>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
     int row_lo, int row_hi, const uint32_t *__restrict__ wmax) {
     __shared__ tile::Lds L;
+    if (MODE == kPanels || MODE == kNext) tile::chain_priority();
     int I, J;
     tile_of<MODE>(r, q, row_lo, row_hi, I, J);
     if (int_exact_in_f32(n, *wmax))

@@ -76,14 +76,21 @@ struct Helper {
     std::mutex mu;                            // one solve enqueues on these at a time
 };
 
-// Point h->copies at three slots sized for n, growing the buffer if needed.
-// False when the memory is not there (the caller then runs single rounds).
+// Bytes of the round-pair copies for an n-vertex matrix: 3 block-row copies
+// and 5 transposed block-column copies, each 128 x 128 q words.
+size_t pair_copies_bytes(int64_t n) {
+    const size_t ldc = (size_t)num_rounds(n) * kRoundB;
+    return (size_t)(kPairRowSlots + 5) * kRoundB * ldc * sizeof(uint32_t);
+}
+
+// Point h->copies at their slots sized for n, growing the buffer if needed
+// (growing synchronises `s` and the helper streams: solves still running on
+// them may read the old buffer).  False when the memory is not there (the
+// caller then runs single rounds).
 bool ensure_copies(Helper *h, int64_t n, hipStream_t s) {
-    const int64_t q = num_rounds(n);
-    const int64_t ldc = (n + 63) / 64 * 64;
-    const size_t row_elems = (size_t)kRoundB * (size_t)ldc;
-    const size_t col_elems = (size_t)q * kRoundB * kRoundB;
-    const size_t need = 3 * (row_elems + col_elems) * sizeof(uint32_t);
+    const int64_t ldc = num_rounds(n) * kRoundB;
+    const size_t slot_elems = (size_t)kRoundB * (size_t)ldc;
+    const size_t need = pair_copies_bytes(n);
     if (h->copies_bytes < need) {
         if (h->copies_buf) {
             // earlier solves on these streams may still read the old buffer
@@ -102,10 +109,8 @@ bool ensure_copies(Helper *h, int64_t n, hipStream_t s) {
         h->copies_bytes = need;
     }
     uint32_t *base = static_cast<uint32_t *>(h->copies_buf);
-    for (int k = 0; k < 3; ++k) {
-        h->copies.row[k] = base + k * (row_elems + col_elems);
-        h->copies.col[k] = h->copies.row[k] + row_elems;
-    }
+    for (int k = 0; k < kPairRowSlots; ++k) h->copies.row[k] = base + k * slot_elems;
+    for (int k = 0; k < 5; ++k) h->copies.colT[k] = base + (kPairRowSlots + k) * slot_elems;
     h->copies.ld = ldc;
     return true;
 }
@@ -272,16 +277,22 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 
     if (pairs) {
         // Round pairs (r, r+1), see apsp_pair.hip.  On S: phases 1-2 of
-        // round r, round r's phase 3 on block row/column r+1 with the
-        // closure of block r+1, phase 2 of round r+1 (copied to a slot);
-        // then, after the previous pair's rest set, the pair pass on block
+        // round r (its block column copied transposed to slot first), round
+        // r's phase 3 on block row/column r+1 with the closure of block r+1,
+        // phase 2 of round r+1 (its panels copied to slot `slot`); then,
+        // after the previous pair's rest set, the pair pass on block
         // rows/columns r+2, r+3 (closing block r+2) and the deferred updates
         // of tiles (x, r), (r, x).  The rest set runs in bands on the helper
         // streams as soon as phase 2 of round r+1 is done.  A band that
         // holds block row prev or prev+1 (the previous pair) waits for every
         // band of the previous pair: all of them read those rows.
+        // Copy slots: `slot` cycles over three, so the previous pair's copies
+        // (read by this pair's deferred updates) are not overwritten before
+        // S has waited for this pair's bands; `first` alternates between two,
+        // its only readers being the pair's own bands, which S waits for
+        // before the pair after next writes it again.
         int64_t prev = -1;
-        int prev_slot = 0, slot = 0;
+        int prev_slot = 0, slot = 0, first = kPairFirstSlot0;
         int64_t r = r0;
         while (r < r1 && err == hipSuccess) {
             if (r + 1 >= r1) {  // the call's last round alone
@@ -301,12 +312,20 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 break;
             }
             const int nx = pair_next_blocks(n, r);
-            phases12(r);
+            {  // phases 1-2 of round r, its block column copied transposed
+                size_t sp1 = open(1, s);
+                if (!diag_closed) chk(launch_phase1(D, n, ld, dtype, r, s));
+                close(sp1, s);
+                diag_closed = false;
+                sp1 = open(2, s);
+                chk(launch_pair_panels(D, n, ld, dtype, r, h->copies, -1, first, s, wmax));
+                close(sp1, s);
+            }
             size_t sp = open(7, s);
-            chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, true, wmax));
+            chk(launch_pair_round_next(D, n, ld, dtype, r, h->copies, first, s, wmax));
             close(sp, s);
             sp = open(2, s);
-            chk(launch_pair_panels(D, n, ld, dtype, r + 1, h->copies, slot, s, wmax));
+            chk(launch_pair_panels(D, n, ld, dtype, r + 1, h->copies, slot, slot, s, wmax));
             close(sp, s);
             chk(hipEventRecord(h->p2_done, s));
             wait_rest(s);
@@ -314,7 +333,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             sp = open(7, s);
             if (nx > 0) {
                 chk(launch_pair_next(D, n, ld, dtype, r, close_next, prev, h->copies, prev_slot,
-                                     s, wmax));
+                                     first, slot, s, wmax));
                 chk(launch_pair_fix(D, n, ld, dtype, r, false, s, wmax));
             }
             close(sp, s);
@@ -333,7 +352,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                 const size_t b = open(5, h->side[g]);
                 chk(launch_pair_rest(D, n, ld, dtype, r, lo, hi, prev, h->copies, prev_slot,
-                                     h->side[g], wmax));
+                                     first, slot, h->side[g], wmax));
                 close(b, h->side[g]);
                 chk(hipEventRecord(h->rest_done[g], h->side[g]));
             }
@@ -341,7 +360,8 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             ++rest_launches;
             prev = r;
             prev_slot = slot;
-            slot = (slot + 1) % 3;
+            slot = (slot + 1) % kPairRowSlots;
+            first = first == kPairFirstSlot0 ? kPairFirstSlot0 + 1 : kPairFirstSlot0;
             r += 2;
         }
         wait_rest(s);

@@ -42,6 +42,14 @@ __device__ __forceinline__ void st4_stream(uint32_t *p, uint4 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
 }
 
+// Wave priority of the launches on the rounds' critical chain (phase 1,
+// phase 2, the tiles the next round's phases read first, the deferred
+// updates).  They share CUs with the bulk phase-3 launches, whose waves are
+// older and almost always ready to issue; at equal priority the chain's waves
+// (a 128-pivot closure with a barrier per pivot above all) then wait for
+// issue slots and the next round's phases start late.
+__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 __device__ __forceinline__ int row_of(int m, int ty) { return (m >> 2) * 64 + ty * 4 + (m & 3); }
 __device__ __forceinline__ int col_of(int e, int tx) { return (e >> 2) * 64 + tx * 4 + (e & 3); }
 
@@ -328,6 +336,129 @@ __device__ __forceinline__ void minplus_tile_ab(uint32_t (&acc)[8][8], const uin
         }
         if (c + 1 < nch) sstore(s ^ 1);
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct staging for full 128 x 128 tiles.  Both operands are copied from
+// global memory into LDS by the load unit itself (global_load_lds_dwordx4:
+// each lane's 16 bytes land at LDS base + 16 * lane), with no register
+// round trip, so a workgroup holds 117 VGPRs per thread instead of ~140 and a
+// CU runs 4 workgroups instead of 3.  That needs both operands k-major in
+// memory: B is (row panel rows are k), A is supplied transposed,
+// AT[k][i] = A[i][k] (a transposed copy of the column panel).  LDS per stage:
+// A[k][i] and B[k][j], 16 k rows of 128 values each, as 16-byte chunks.
+// ---------------------------------------------------------------------------
+struct LdsDirect {
+    uint4 A[2][KC][TB / 4];
+    uint4 B[2][KC][TB / 4];
+};
+static_assert(sizeof(LdsDirect) == sizeof(Lds), "direct staging reuses the tile LDS");
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ void dma16(const uint32_t *g, uint4 *l) {
+    __builtin_amdgcn_global_load_lds(g, (lds_void_t *)l, 16, 0, 0);
+}
+
+// acc = min(acc, A (x) B) for a full 128 x 128 output tile at (i0, j0), k in
+// [0, kw), kw a multiple of 16, with A[i][k] = AT[k][i] taken from AT0 for
+// k < ksplit and from AT1 (row k - ksplit) otherwise (ksplit a multiple of 16;
+// the two column panels of a round pair), both with leading dimension ldat,
+// and B[k][j] = B[k * ldb + j0 + j].  Every row read is 16-byte aligned and
+// in bounds (the caller guarantees full tiles).  One barrier per stage; the
+// stage after next is loaded while a stage is computed; every thread returns
+// after a final barrier.  Same candidates and minima as minplus_tile_ab, so
+// the same bits.
+template <class Op>
+__device__ __forceinline__ void minplus_tile_direct(uint32_t (&acc)[8][8], const uint32_t *AT0,
+                                                    const uint32_t *AT1, int ksplit, int64_t ldat,
+                                                    const uint32_t *B, int64_t ldb, int64_t i0,
+                                                    int64_t j0, int kw, Lds &Lraw) {
+    LdsDirect &L = reinterpret_cast<LdsDirect &>(Lraw);
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave: LDS base must be uniform
+    const int l = t & 63;
+    // a wave's two loads per operand and stage: chunks p = 128 w + 64 h + l,
+    // chunk p = (k row p / 32, 16-byte column chunk p % 32)
+    // (32-bit element offsets from uniform bases: the caller keeps 16 ld + i0,
+    // 16 ld + j0 below 2^30)
+    const int p0 = 128 * w + l, p1 = p0 + 64;
+    const uint32_t a_off0 = (uint32_t)(p0 >> 5) * (uint32_t)ldat + (uint32_t)i0 + (p0 & 31) * 4;
+    const uint32_t a_off1 = a_off0 + 2u * (uint32_t)ldat;
+    const uint32_t b_off0 = (uint32_t)(p0 >> 5) * (uint32_t)ldb + (uint32_t)j0 + (p0 & 31) * 4;
+    const uint32_t b_off1 = b_off0 + 2u * (uint32_t)ldb;
+    auto issue = [&](int c, int s) {
+        const int k0 = c * KC;
+        const uint32_t *ab = k0 < ksplit ? AT0 + (int64_t)k0 * ldat : AT1 + (int64_t)(k0 - ksplit) * ldat;
+        const uint32_t *bb = B + (int64_t)k0 * ldb;
+        uint4 *la = &L.A[s][0][0] + 128 * w;
+        uint4 *lb = &L.B[s][0][0] + 128 * w;
+        dma16(ab + a_off0, la);
+        dma16(ab + a_off1, la + 64);
+        dma16(bb + b_off0, lb);
+        dma16(bb + b_off1, lb + 64);
+    };
+    const int nch = kw / KC;
+    issue(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int s = c & 1;
+        // buffer s^1 was last read in stage c-1, which every wave has left
+        if (c + 1 < nch) issue(c + 1, s ^ 1);
+#pragma unroll 2
+        for (int p = 0; p < KC / 2; ++p) {
+            uint32_t a0[8], a1[8], b0[8], b1[8];
+            // rows row_of(m, ty): ty*4 .. +3 (m < 4) and 64 + ty*4 .. +3
+            const uint4 x00 = L.A[s][2 * p][ty], x01 = L.A[s][2 * p][16 + ty];
+            const uint4 x10 = L.A[s][2 * p + 1][ty], x11 = L.A[s][2 * p + 1][16 + ty];
+            a0[0] = x00.x; a0[1] = x00.y; a0[2] = x00.z; a0[3] = x00.w;
+            a0[4] = x01.x; a0[5] = x01.y; a0[6] = x01.z; a0[7] = x01.w;
+            a1[0] = x10.x; a1[1] = x10.y; a1[2] = x10.z; a1[3] = x10.w;
+            a1[4] = x11.x; a1[5] = x11.y; a1[6] = x11.z; a1[7] = x11.w;
+            const uint4 b00 = L.B[s][2 * p][tx], b01 = L.B[s][2 * p][16 + tx];
+            const uint4 b10 = L.B[s][2 * p + 1][tx], b11 = L.B[s][2 * p + 1][16 + tx];
+            b0[0] = b00.x; b0[1] = b00.y; b0[2] = b00.z; b0[3] = b00.w;
+            b0[4] = b01.x; b0[5] = b01.y; b0[6] = b01.z; b0[7] = b01.w;
+            b1[0] = b10.x; b1[1] = b10.y; b1[2] = b10.z; b1[3] = b10.w;
+            b1[4] = b11.x; b1[5] = b11.y; b1[6] = b11.z; b1[7] = b11.w;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    acc[m][e] = Op::min3(acc[m][e], Op::add(a0[m], b0[e]), Op::add(a1[m], b1[e]));
+        }
+        // the next stage's operands are in LDS and every wave is done with this one
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+}
+
+// Store the mr x nc tile transposed: dst[col * ldd + i0 + row] = C[row][col]
+// (Op::out applied), the layout minplus_tile_direct takes its A operand in.
+// dst and ldd must keep 16-byte alignment at i0 (i0 a multiple of 4).
+template <class Op>
+__device__ __forceinline__ void store_acc_t(const uint32_t (&acc)[8][8], uint32_t *dst, int64_t ldd,
+                                            int64_t i0, int mr, int nc) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int col = col_of(e, tx);
+        if (col >= nc) continue;
+        uint32_t *drow = dst + (int64_t)col * ldd + i0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = h * 64 + ty * 4;
+            if (row + 3 < mr) {
+                st4(drow + row, make_uint4(Op::out(acc[h * 4 + 0][e]), Op::out(acc[h * 4 + 1][e]),
+                                           Op::out(acc[h * 4 + 2][e]), Op::out(acc[h * 4 + 3][e])));
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (row + u < mr) drow[row + u] = Op::out(acc[h * 4 + u][e]);
+            }
+        }
     }
 }
 

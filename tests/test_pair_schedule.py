@@ -160,16 +160,20 @@ class _Model:
         self.rng = random.Random(seed)
 
     # tasks: closures returning a writer
-    def upd(self, i, j, kblocks, pend=None, close=False):
+    def upd(self, i, j, kblocks, pend=None, close=False, acopy=None):
+        """acopy: {k: copy} takes block (i, k) of the left operand from that
+        copy of block column k (the direct-staged rest pass) instead of the
+        matrix."""
         D, b = self.D, self.b
 
         def read():
             acc = _blk(D, b, i, j).copy()
             if pend is not None:
-                row, col, k = pend
-                acc = _mp(acc, col[(i, k)].copy(), row[(k, j)].copy())
+                row, col = pend
+                acc = _mp(acc, col[("c", i)].copy(), row[("r", j)].copy())
             for k in kblocks:
-                acc = _mp(acc, _blk(D, b, i, k).copy(), _blk(D, b, k, j).copy())
+                left = acopy[k][("c", i)] if acopy is not None else _blk(D, b, i, k)
+                acc = _mp(acc, left.copy(), _blk(D, b, k, j).copy())
             if close:
                 acc = _closure(acc)
 
@@ -178,7 +182,11 @@ class _Model:
             return write
         return read
 
-    def panel(self, r, i, j, copy=None):
+    def panel(self, r, i, j, copy=None, colcopy=None):
+        """copy: block-row and block-column copy slot (the second round of a
+        pair); colcopy: block-column copy slot only (the first round).  A slot
+        is one buffer, overwritten in place when it is used again: block row
+        tiles at ("r", j), block column tiles at ("c", i)."""
         D, b = self.D, self.b
 
         def read():
@@ -188,7 +196,9 @@ class _Model:
             def write():
                 _blk(D, b, i, j)[:] = out
                 if copy is not None:
-                    copy[(i, j)] = out.copy()
+                    copy[("r", j) if i == r else ("c", i)] = out.copy()
+                if colcopy is not None and j == r:
+                    colcopy[("c", i)] = out.copy()
             return write
         return read
 
@@ -270,12 +280,17 @@ class _Model:
         assert all(heads[s] == len(self.q[s]) for s in range(len(self.q)))
 
 
-def _pair_schedule(m, q, r0, r1, bands):
+def _pair_schedule(m, q, r0, r1, bands, direct=True, ring=3, first_ring=2):
     """The runtime's enqueue order for rounds r0..r1-1 in pairs (stream 0 is
-    the caller's stream, 1.. the band streams)."""
+    the caller's stream, 1.. the band streams).  direct: the rest pass takes
+    the column panels of its rounds from their copies (the direct-staged
+    kernel), as the runtime does for aligned fp32 matrices of full tiles.
+    ring / first_ring: copy slots of a pair's second / first round (3 / 2 in
+    the runtime; the tests shorten them to see that the model notices)."""
     S, H = 0, list(range(1, bands + 1))
-    copies = [None, None, None]
-    prev, prev_slot, slot = -1, 0, 0
+    copies = [{} for _ in range(ring)]
+    firsts = [{} for _ in range(first_ring)]
+    prev, prev_slot, slot, first = -1, 0, 0, 0
     rest_pending, diag_closed = False, False
 
     def band(g):
@@ -286,17 +301,17 @@ def _pair_schedule(m, q, r0, r1, bands):
             for g in range(bands):
                 m.wait(st, ("rest", g))
 
-    def phases12(r):
+    def phases12(r, colcopy=None):
         nonlocal diag_closed
         if not diag_closed:
             m.launch(S, [m.close_task(r)])
         diag_closed = False
-        m.launch(S, [m.panel(r, i, j) for i, j in _panel_tiles(r, q)])
+        m.launch(S, [m.panel(r, i, j, colcopy=colcopy) for i, j in _panel_tiles(r, q)])
 
     def pend(i, j):
         if _pending(i, j, prev):
             c = copies[prev_slot]
-            return (c, c, prev + 1)
+            return (c, c)
         return None
 
     def fix(r, final):
@@ -316,10 +331,10 @@ def _pair_schedule(m, q, r0, r1, bands):
             r += 1
             break
         nx = _nxt(q, r)
-        phases12(r)
+        phases12(r, firsts[first])
         m.launch(S, [m.upd(i, j, [r], close=(i == j == r + 1)) for i, j in _next_tiles(r, q)])
-        copies[slot] = {}
         m.launch(S, [m.panel(r + 1, i, j, copies[slot]) for i, j in _panel_tiles(r + 1, q)])
+        acopy = {r: firsts[first], r + 1: copies[slot]} if direct else None
         m.record(S, "p2")
         wait_rest(S)
         close_next = nx > 0 and r + 2 < r1
@@ -337,12 +352,12 @@ def _pair_schedule(m, q, r0, r1, bands):
         for g in range(bands):
             lo, hi = band(g)
             m.wait(H[g], "p2")
-            m.launch(H[g], [m.upd(i, j, [r, r + 1], pend(i, j))
+            m.launch(H[g], [m.upd(i, j, [r, r + 1], pend(i, j), acopy=acopy)
                             for i, j in (_rest2_tile(w, r, q, lo, hi)
                                          for w in range(_rest2_count(r, q, lo, hi)))])
             m.record(H[g], ("rest", g))
         rest_pending = True
-        prev, prev_slot, slot = r, slot, (slot + 1) % 3
+        prev, prev_slot, slot, first = r, slot, (slot + 1) % ring, (first + 1) % first_ring
         r += 2
     wait_rest(S)
     if prev >= 0:
@@ -354,7 +369,8 @@ def _pair_schedule(m, q, r0, r1, bands):
                                      (8, 0, 8), (9, 0, 9), (10, 0, 7), (10, 3, 10), (11, 1, 11),
                                      (12, 2, 4), (13, 0, 13), (12, 5, 12)])
 @pytest.mark.parametrize("bands", [1, 2, 3])
-def test_pair_schedule_model_is_bit_exact(q, r0, r1, bands):
+@pytest.mark.parametrize("direct", [False, True])
+def test_pair_schedule_model_is_bit_exact(q, r0, r1, bands, direct):
     b = 3
     n = q * b
     rng = np.random.default_rng(1000 * q + 10 * r0 + r1)
@@ -366,9 +382,31 @@ def test_pair_schedule_model_is_bit_exact(q, r0, r1, bands):
     for seed in range(3):
         D = start.copy()
         m = _Model(D, b, 1 + bands, seed * 97 + q)
-        _pair_schedule(m, q, r0, r1, bands)
+        _pair_schedule(m, q, r0, r1, bands, direct)
         m.run()
         assert np.array_equal(D.view(np.int32), ref.view(np.int32)), seed
+
+
+@pytest.mark.parametrize("ring,first_ring", [(2, 2), (3, 1)])
+def test_pair_schedule_model_catches_a_short_copy_ring(ring, first_ring):
+    """One copy slot fewer than the runtime uses (for either round of a pair)
+    lets a pair overwrite a copy that a running band still reads: the model
+    sees it in some interleavings."""
+    b, q, bands = 3, 14, 2
+    n = q * b
+    rng = np.random.default_rng(11)
+    W = rng.uniform(0.5, 10.0, size=(n, n)).astype(np.float32)
+    W[rng.random((n, n)) > 0.3] = np.inf
+    np.fill_diagonal(W, 0.0)
+    ref = oracle.blocked(W, b)
+    differs = 0
+    for seed in range(24):
+        D = W.copy()
+        m = _Model(D, b, 1 + bands, seed)
+        _pair_schedule(m, q, 0, q, bands, True, ring, first_ring)
+        m.run()
+        differs += not np.array_equal(D.view(np.int32), ref.view(np.int32))
+    assert differs > 0
 
 
 def test_pair_schedule_model_catches_a_missing_wait():
