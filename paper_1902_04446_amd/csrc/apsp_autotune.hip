@@ -52,6 +52,15 @@ __global__ void k_fill_synth(uint32_t *buf, int64_t count, uint32_t seed, int dt
 
 int batched_bucket(int64_t n) { return n <= 512 ? (n <= 64 ? 0 : (int)((n - 1) / 64)) : 8; }
 
+void batched_tuning_snapshot(int32_t *table) {
+    int dev = 0;
+    const bool have = current_device(&dev);
+    for (int b = 0; b < kTuneBuckets; ++b) {
+        const int v = have ? g_table[dev][b].load(std::memory_order_relaxed) : 0;
+        table[b] = v == 64 ? 64 : kRoundB;
+    }
+}
+
 int batched_tile(int64_t n) {
     int dev = 0;
     if (!current_device(&dev)) return kRoundB;

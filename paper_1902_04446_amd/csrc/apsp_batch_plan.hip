@@ -3,6 +3,9 @@
 // built on the host once and kept in device memory, so running a plan is
 // nothing but kernel launches (and can be captured in a HIP graph).
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -33,8 +36,8 @@ namespace apsp {
 
 // Build the plan's host tables.  Every graph gets a round width (64 or 128):
 // `tile` forces one for all, else `table` (per size bucket) when given, else
-// the device's tuning table.  Launch 0 is phase 1 of round 0 for every
-// graph; launches 2r+1 and 2r+2 are phases 2 and 3 of round r for every
+// the device's tuning table (read once).  Launch 0 is phase 1 of round 0 for
+// every graph; launches 2r+1 and 2r+2 are phases 2 and 3 of round r for every
 // graph that has a round r at its own width, with the closure of diagonal
 // block r+1 fused into phase 3.  int32 plans also list the 128 x 128 tiles
 // of every graph for the weight scan that precedes the solve.
@@ -43,19 +46,26 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
                    std::vector<BatchItem> &items) {
     descs.clear();
     items.clear();
+    p.launches.clear();
+    int32_t dev_table[kTuneBuckets];
+    if (!tile && !table) {
+        batched_tuning_snapshot(dev_table);
+        table = dev_table;
+    }
     for (int32_t g = 0; g < count; ++g) {
         if (ns[g] == 0) continue;
         BatchDesc d;
         d.ptr = static_cast<uint32_t *>(ptrs[g]);
         d.ld = lds ? lds[g] : (ns[g] > 1 ? ns[g] : 1);
         d.n = ns[g];
-        d.tile = tile ? tile : table ? table[batched_bucket(ns[g])] : batched_tile(ns[g]);
+        d.tile = tile ? tile : table[batched_bucket(ns[g])];
         descs.push_back(d);
     }
     const int G = (int)descs.size();
     p.graphs = G;
     if (G == 0) return APSP_OK;
-    auto rounds_of = [&](int g) { return (descs[g].n + descs[g].tile - 1) / descs[g].tile; };
+    std::vector<int> q(G);
+    for (int g = 0; g < G; ++g) q[g] = (descs[g].n + descs[g].tile - 1) / descs[g].tile;
 
     // Balance graphs over the 8 XCDs by work (longest first, least loaded
     // XCD), so each XCD's item list of every launch is about as long.
@@ -66,15 +76,22 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
     std::vector<int> xcd(G, 0);
     double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int qmax = 0;
+    int64_t total = 0;
     for (int g : order) {
-        const double q = rounds_of(g), w = descs[g].tile;
+        const double qq = q[g], w = descs[g].tile;
         const int best = (int)(std::min_element(load, load + 8) - load);
         xcd[g] = best;
-        load[best] += q * q * q * w * w * w;
-        qmax = std::max(qmax, rounds_of(g));
+        load[best] += qq * qq * qq * w * w * w;
+        qmax = std::max(qmax, q[g]);
+        total += 1 + (int64_t)q[g] * ((int64_t)q[g] * q[g] - 1);
     }
+    // graphs of each width, largest first: those with a round r are a prefix
+    std::vector<int> by_width[2];
+    for (int g : order) by_width[descs[g].tile == 64 ? 1 : 0].push_back(g);
 
+    items.reserve((size_t)total);
     std::vector<BatchItem> per[8];
+    for (auto &v : per) v.reserve((size_t)(total / 8 / std::max(1, 2 * qmax + 1) + 16));
     auto flush = [&](int r, bool close_only) {
         apsp_batch_plan::Launch L;
         L.r = r;
@@ -96,55 +113,55 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
     // Within a launch the longest items go first, where they overlap the
     // rest of the launch instead of its tail: 128-wide before 64-wide, and in
     // phase 3 the diagonal block r+1 (whose workgroup also closes it) first.
-    const int widths[2] = {128, 64};
-    for (int W : widths)
-        for (int g : order)
-            if (descs[g].tile == W) push(g, 0, 0);  // phase 1 of round 0, every graph
+    for (int w = 0; w < 2; ++w)
+        for (int g : by_width[w]) push(g, 0, 0);  // phase 1 of round 0, every graph
     flush(0, true);
     for (int r = 0; r < qmax; ++r) {
-        for (int W : widths)
-            for (int g : order) {  // phase 2 of round r
-                const int q = rounds_of(g);
-                if (descs[g].tile != W || q <= r || q == 1) continue;
-                for (int J = 0; J < q; ++J)
+        for (int w = 0; w < 2; ++w)
+            for (int g : by_width[w]) {  // phase 2 of round r
+                const int qg = q[g];
+                if (qg <= r) break;  // and every later (smaller) graph of this width
+                if (qg == 1) continue;
+                for (int J = 0; J < qg; ++J)
                     if (J != r) push(g, r, J);
-                for (int I = 0; I < q; ++I)
+                for (int I = 0; I < qg; ++I)
                     if (I != r) push(g, I, r);
             }
         flush(r, false);
-        for (int W : widths) {  // phase 3 of round r
-            for (int g : order) {
-                const int q = rounds_of(g);
-                if (descs[g].tile != W || q <= r || q == 1) continue;
-                if (r + 1 < q) push(g, r + 1, r + 1);
+        for (int w = 0; w < 2; ++w) {  // phase 3 of round r
+            for (int g : by_width[w]) {
+                const int qg = q[g];
+                if (qg <= r) break;
+                if (qg > 1 && r + 1 < qg) push(g, r + 1, r + 1);
             }
-            for (int g : order) {
-                const int q = rounds_of(g);
-                if (descs[g].tile != W || q <= r || q == 1) continue;
-                for (int I = 0; I < q; ++I)
-                    for (int J = 0; J < q; ++J)
+            for (int g : by_width[w]) {
+                const int qg = q[g];
+                if (qg <= r) break;
+                if (qg == 1) continue;
+                for (int I = 0; I < qg; ++I)
+                    for (int J = 0; J < qg; ++J)
                         if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
             }
         }
         flush(r, false);
     }
     if (p.dtype == APSP_I32) {
-        std::vector<BatchItem> scan[8];
+        for (auto &v : per) v.clear();
         int64_t next = 0;
         for (int g = 0; g < G; ++g) {
-            const int q = (descs[g].n + kRoundB - 1) / kRoundB;
-            for (int I = 0; I < q; ++I)
-                for (int J = 0; J < q; ++J) {
+            const int qs = (descs[g].n + kRoundB - 1) / kRoundB;
+            for (int I = 0; I < qs; ++I)
+                for (int J = 0; J < qs; ++J) {
                     BatchItem it;
                     it.graph = g;
                     it.ij = (I << 16) | J;
-                    scan[next++ & 7].push_back(it);
+                    per[next++ & 7].push_back(it);
                 }
         }
         for (int x = 0; x < 8; ++x) {
             p.scan.offset[x] = (int32_t)items.size();
-            p.scan.count[x] = (int32_t)scan[x].size();
-            items.insert(items.end(), scan[x].begin(), scan[x].end());
+            p.scan.count[x] = (int32_t)per[x].size();
+            items.insert(items.end(), per[x].begin(), per[x].end());
         }
     }
     p.items = (int64_t)items.size();
@@ -176,13 +193,46 @@ int32_t check_batch(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
     return APSP_OK;
 }
 
+// The device tables of a plan are one buffer: the graph descriptors, then
+// (int32) one word per graph for its largest finite weight, then (16-byte
+// aligned) the work items.
+struct TableLayout {
+    size_t wmax_off, items_off, total;
+};
+
+TableLayout table_layout(size_t graphs, size_t items, int32_t dtype) {
+    TableLayout t;
+    t.wmax_off = graphs * sizeof(apsp::BatchDesc);
+    const size_t wb = dtype == APSP_I32 ? graphs * sizeof(uint32_t) : 0;
+    t.items_off = (t.wmax_off + wb + 15) / 16 * 16;
+    t.total = t.items_off + items * sizeof(apsp::BatchItem);
+    return t;
+}
+
+// The tables in one host buffer, laid out as on the device (the weight words
+// are left for the scan launch to fill).
+void pack_tables(const std::vector<apsp::BatchDesc> &descs,
+                 const std::vector<apsp::BatchItem> &items, const TableLayout &t,
+                 std::vector<unsigned char> &host) {
+    host.resize(t.total);
+    std::memcpy(host.data(), descs.data(), descs.size() * sizeof(apsp::BatchDesc));
+    std::memset(host.data() + t.wmax_off, 0, t.items_off - t.wmax_off);
+    std::memcpy(host.data() + t.items_off, items.data(), items.size() * sizeof(apsp::BatchItem));
+}
+
+void point_tables(apsp_batch_plan *p, void *base, const TableLayout &t) {
+    unsigned char *b = static_cast<unsigned char *>(base);
+    p->d_descs = reinterpret_cast<apsp::BatchDesc *>(b);
+    p->d_wmax = p->dtype == APSP_I32 ? reinterpret_cast<uint32_t *>(b + t.wmax_off) : nullptr;
+    p->d_items = reinterpret_cast<apsp::BatchItem *>(b + t.items_off);
+}
+
 void free_plan_buffers(apsp_batch_plan *p, hipStream_t s) {
-    if (p->stream_ordered) {
-        if (p->d_descs) (void)hipFreeAsync(p->d_descs, s);
-        if (p->d_items) (void)hipFreeAsync(p->d_items, s);
-    } else {
-        if (p->d_descs) (void)hipFree(p->d_descs);
-        if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_descs) {
+        if (p->stream_ordered)
+            (void)hipFreeAsync(p->d_descs, s);
+        else
+            (void)hipFree(p->d_descs);
     }
     p->d_descs = nullptr;
     p->d_items = nullptr;
@@ -214,34 +264,21 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
             delete p;
             return APSP_ERR_DEVICE;
         }
-        const size_t db = descs.size() * sizeof(apsp::BatchDesc) +
-                          (dtype == APSP_I32 ? descs.size() * sizeof(uint32_t) : 0);
-        const size_t ib = items.size() * sizeof(apsp::BatchItem);
-        hipError_t e1, e2;
-        if (stream_ordered) {
-            e1 = hipMallocAsync(reinterpret_cast<void **>(&p->d_descs), db, s);
-            e2 = hipMallocAsync(reinterpret_cast<void **>(&p->d_items), ib, s);
-        } else {
-            e1 = hipMalloc(reinterpret_cast<void **>(&p->d_descs), db);
-            e2 = hipMalloc(reinterpret_cast<void **>(&p->d_items), ib);
-        }
-        if (e1 != hipSuccess || e2 != hipSuccess) {
+        const TableLayout t = table_layout(descs.size(), items.size(), dtype);
+        std::vector<unsigned char> host;
+        pack_tables(descs, items, t, host);
+        void *buf = nullptr;
+        const hipError_t e =
+            stream_ordered ? hipMallocAsync(&buf, t.total, s) : hipMalloc(&buf, t.total);
+        if (e != hipSuccess) {
             (void)hipGetLastError();
-            free_plan_buffers(p, s);
             delete p;
             return APSP_ERR_NO_MEMORY;
         }
-        if (dtype == APSP_I32) p->d_wmax = reinterpret_cast<uint32_t *>(p->d_descs + descs.size());
-        const size_t dcopy = descs.size() * sizeof(apsp::BatchDesc);
-        // Pageable sources: both copies have consumed the host vectors when
-        // they return.
-        if (hipMemcpyAsync(p->d_descs, descs.data(), dcopy, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(p->d_items, items.data(), ib, hipMemcpyHostToDevice, s) != hipSuccess) {
-            free_plan_buffers(p, s);
-            delete p;
-            return APSP_ERR_DEVICE;
-        }
-        if (!stream_ordered && hipStreamSynchronize(s) != hipSuccess) {
+        point_tables(p, buf, t);
+        // Pageable source: the copy has consumed the host buffer when it returns.
+        if (hipMemcpyAsync(buf, host.data(), t.total, hipMemcpyHostToDevice, s) != hipSuccess ||
+            (!stream_ordered && hipStreamSynchronize(s) != hipSuccess)) {
             free_plan_buffers(p, s);
             delete p;
             return APSP_ERR_DEVICE;

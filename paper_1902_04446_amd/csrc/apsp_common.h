@@ -215,6 +215,9 @@ hipError_t launch_batched_items(const BatchDesc *descs, const BatchItem *items,
 int batched_tile(int64_t n);
 constexpr int kTuneBuckets = 9;  // bucket b < 8: n in (64b, 64b + 64]; bucket 8: n > 512
 int batched_bucket(int64_t n);
+// The current device's batched width of every bucket (kTuneBuckets entries;
+// 128 everywhere without a device).
+void batched_tuning_snapshot(int32_t *table);
 // Plan with the round width of each graph taken from `table` (kTuneBuckets
 // entries, 64 or 128), for the batched autotuner; arguments as
 // apsp_batched_plan_create.
@@ -234,6 +237,8 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
 
 // Record the failing HIP call of the current thread (apsp_last_error()).
 void note_error(const char *what, hipError_t e);
+// Record a message for apsp_last_error() (a request the library refused).
+void note_message(const char *what);
 
 // ---- round scheduler (apsp_runtime.hip) ------------------------------------
 // Per-phase elapsed milliseconds of a profiled solve (see apsp_solve_profiled).
