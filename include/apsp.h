@@ -193,6 +193,35 @@ int32_t apsp_solve_batched_ex(void *const *ptrs, const int32_t *ns, const int64_
                               int32_t count, int32_t dtype, void *stream);
 
 /*
+ * apsp_solve_batched_noalloc -- apsp_solve_batched_ex for callers that cannot
+ * allocate device memory (code enqueued in tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same kernels, same results, but
+ * the descriptor and work-item tables go to a fixed device workspace of
+ * APSP_NOALLOC_WORKSPACE_BYTES that the library holds on every GPU it runs
+ * on (a file-scope device array, kept until the process ends) instead of
+ * stream-ordered allocations.  No hipMalloc, hipFree or other device
+ * allocation is made.  The host tables are built in per-thread host buffers
+ * that keep their size between calls.
+ * Limit: the tables take 24 bytes per non-empty graph, 4 more per graph for
+ * int32, rounded up to 16, plus 8 bytes per work item, where a graph with
+ * q = ceil(n / b) rounds at its batched width b has 1 + q (q^2 - 1) items
+ * (int32 adds ceil(n / 128)^2 for the weight scan).  A batch whose tables do
+ * not fit is refused with APSP_ERR_UNSUPPORTED before any HIP call (the
+ * 4096-graph batch of n <= 512 needs about 0.7 MiB); apsp_last_error() then
+ * states the size needed.
+ * Every call on a GPU uses that GPU's one workspace, and the next call
+ * overwrites it: calls enqueued on the same stream are ordered, but calls
+ * that may overlap on one GPU (different streams, or host threads racing on
+ * one stream) race on the tables and must be serialised by the caller.
+ * The tables are copied from pageable host memory (hipMemcpyAsync), so the
+ * call returns once they are consumed; it is not meant for HIP graph capture.
+ * Returns as apsp_solve_batched_ex, or APSP_ERR_UNSUPPORTED.
+ */
+#define APSP_NOALLOC_WORKSPACE_BYTES (8 << 20)
+int32_t apsp_solve_batched_noalloc(void *const *ptrs, const int32_t *ns, const int64_t *lds,
+                                   int32_t count, int32_t dtype, void *stream);
+
+/*
  * Reusable batched plans.  apsp_batched_plan_create checks the arguments as
  * apsp_solve_batched_ex does, builds the descriptor and work-item tables on
  * the host, copies them into library-owned device memory (hipMalloc) and

@@ -15,7 +15,8 @@ import os
 
 __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
-    "solve", "solve_profiled", "solve_rounds", "solve_batched", "BatchPlan", "validate",
+    "solve", "solve_profiled", "solve_rounds", "solve_batched", "solve_batched_noalloc",
+    "BatchPlan", "validate",
     "minplus", "solve_squaring", "squarings", "solve_symmetric",
     "round_width", "batched_round_width", "num_rounds", "version",
     "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
@@ -66,6 +67,7 @@ def _load() -> ctypes.CDLL:
         "apsp_set_round_pair_threshold": ([i32], i32),
         "apsp_solve_batched": ([vp, vp, i32, vp], i32),
         "apsp_solve_batched_ex": ([vp, vp, vp, i32, i32, vp], i32),
+        "apsp_solve_batched_noalloc": ([vp, vp, vp, i32, i32, vp], i32),
         "apsp_validate": ([vp, i64, i64, i32, vp], i32),
         "apsp_batched_plan_create": ([vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "apsp_batched_plan_run": ([vp, vp], i32),
@@ -263,6 +265,22 @@ def solve_batched(mats, stream=None):
     with torch.cuda.device(dev):
         _check(_LIB.apsp_solve_batched_ex(ptrs, ns, lds, len(mats), dt, _stream(stream)),
                "apsp_solve_batched_ex")
+    return mats
+
+
+def solve_batched_noalloc(mats, stream=None):
+    """solve_batched without any device allocation: the tables go to the
+    library's fixed per-GPU workspace (apsp_solve_batched_noalloc; calls that
+    overlap on one GPU race on it)."""
+    import torch
+
+    mats = list(mats)
+    if not mats:
+        return mats
+    ptrs, ns, lds, dt, dev = _batch_arrays(mats)
+    with torch.cuda.device(dev):
+        _check(_LIB.apsp_solve_batched_noalloc(ptrs, ns, lds, len(mats), dt, _stream(stream)),
+               "apsp_solve_batched_noalloc")
     return mats
 
 

@@ -19,6 +19,8 @@ void note_error(const char *what, hipError_t e) {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
 }
 
+void note_message(const char *what) { snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
+
 }  // namespace apsp
 
 namespace {

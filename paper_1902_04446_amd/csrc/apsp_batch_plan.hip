@@ -378,3 +378,83 @@ int32_t apsp_solve_batched(void *const *ptrs, const int32_t *ns, int32_t count, 
 }
 
 }  // extern "C"
+
+// ---- allocation-free batched solve ------------------------------------------
+// apsp_solve_batched_noalloc keeps its tables in this file-scope device array
+// instead of memory it allocates.  Each GPU the library runs on has its own
+// copy, held until the process ends.  Host code never passes the array's name
+// to a kernel or a copy (on the host it only names the symbol): it uses the
+// device address hipGetSymbolAddress returns, looked up once per device.
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)APSP_NOALLOC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxScratchDevices] = {};
+
+// The current device's copy of `scratch` (its device address), or null.
+void *scratch_for_current_device(hipError_t *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxScratchDevices)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" int32_t apsp_solve_batched_noalloc(void *const *ptrs, const int32_t *ns,
+                                              const int64_t *lds, int32_t count, int32_t dtype,
+                                              void *stream) {
+    const int32_t st = check_batch(ptrs, ns, lds, count, dtype);
+    if (st != APSP_OK) return st;
+    if (count == 0) return APSP_OK;
+    // host tables in per-thread buffers that keep their capacity between calls
+    thread_local std::vector<apsp::BatchDesc> descs;
+    thread_local std::vector<apsp::BatchItem> items;
+    thread_local std::vector<unsigned char> host;
+    apsp_batch_plan p;
+    p.dtype = dtype;
+    apsp::plan_build(p, ptrs, ns, lds, count, 0, nullptr, descs, items);
+    if (descs.empty()) return APSP_OK;  // every graph empty: no HIP call
+    const TableLayout t = table_layout(descs.size(), items.size(), dtype);
+    if (t.total > kNoAllocBytes) {
+        char msg[160];
+        snprintf(msg, sizeof(msg),
+                 "batch tables need %zu bytes; the allocation-free workspace holds %zu",
+                 t.total, kNoAllocBytes);
+        apsp::note_message(msg);
+        return APSP_ERR_UNSUPPORTED;
+    }
+    hipError_t e = hipSuccess;
+    void *ws = scratch_for_current_device(&e);
+    if (!ws) {
+        apsp::note_error("hipGetSymbolAddress(scratch)", e);
+        return APSP_ERR_DEVICE;
+    }
+    pack_tables(descs, items, t, host);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // Pageable source: the copy has consumed the host buffer when it returns.
+    e = hipMemcpyAsync(ws, host.data(), t.total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        apsp::note_error("hipMemcpyAsync to the allocation-free workspace", e);
+        return APSP_ERR_DEVICE;
+    }
+    point_tables(&p, ws, t);
+    return plan_run(&p, s);
+}
