@@ -72,7 +72,8 @@ enum {
  *   ld     leading dimension in elements, ld >= max(n, 1).
  *   dtype  APSP_I32 or APSP_F32.
  *   stream hipStream_t to enqueue on (NULL = default stream).
- * For n > 256 the phases of round r+1 overlap the bulk of round r's phase 3
+ * Rounds are 64 wide up to n = 5120 and 128 wide above (apsp_round_width).
+ * From 3 rounds on (64 rounds of width 64) the phases of round r+1 overlap the bulk of round r's phase 3
  * on library-owned helper streams (one set per device and caller stream,
  * created on first use and kept; from 64 rounds up that phase 3 runs as two
  * bands of block rows on two of them); the call makes `stream` wait for that
@@ -85,10 +86,13 @@ enum {
  * phase 3 runs in pairs of rounds: one pass per tile with k over both rounds' blocks, the second
  * round's update of the first round's block row and column deferred and
  * applied from a copy of its panels (the result is the same, bit for bit).
- * The copies take 3 x (128 x ceil64(n) + 128 x 128 x q) x 4 bytes (48 MiB at
- * n = 16384, 768 MiB at n = 262144), allocated with the helper streams on
- * first need and grown (after synchronising those streams) for a larger n;
- * when they cannot be allocated the call runs single rounds instead.
+ * Phase 2 of every round also writes its block column transposed, which the
+ * bulk of phase 3 reads for fp32 matrices with n a multiple of 128 and
+ * 16-byte aligned rows.  The copies take 8 x 128 x 128q x 4 bytes (64 MiB at
+ * n = 16384, 1 GiB at n = 262144), allocated with the helper streams on
+ * first need and grown for a larger n; growing synchronises `stream` and the
+ * helper streams inside the call (solves still running on them may read the
+ * old copies).  When they cannot be allocated the call runs single rounds.
  * Nothing else is allocated.
  * Solves enqueued on the same stream from several host threads are
  * serialised by the library.
@@ -152,16 +156,33 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
  * them (Sec. 4): phases 2 and 3 update blocks (I, J) with I <= J, reading the
  * transposes of upper blocks where the method needs a lower one; the strict
  * lower triangle is then filled from the upper one.  Only the upper triangle
- * of the input is read (the lower is overwritten).  For a symmetric input the
- * result equals apsp_solve's bit for bit (fp32 addition commutes), with
- * about half of its phase-2/3 work.  Single stream, no lookahead;
+ * of the input is read (the lower is overwritten).  Rounds are 128 wide.
+ * For a symmetric input the result equals the 128-wide blocked method's bit
+ * for bit (fp32 addition commutes; apsp_solve's whenever apsp_round_width(n)
+ * is 128), with about half of its phase-2/3 work.  Single stream, no lookahead;
  * asynchronous; allocates nothing.  Returns as apsp_solve.
  */
 int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
 
-/* Round width b used by apsp_solve / apsp_solve_rounds (currently 128 for
- * every n and dtype); q = ceil(n / b) rounds.  Returns 0 for a bad dtype. */
+/* Round width b used by apsp_solve / apsp_solve_rounds / apsp_solve_profiled
+ * for an n-vertex matrix: 64 for n <= the width-64 limit (default 5120;
+ * apsp_set_width64_max_n), 128 above it; q = ceil(n / b) rounds.  Sec. 4
+ * leaves b to the user or a tuner.  Small solves are bound by the chain of
+ * dependent launches of each round, which 64-wide rounds shorten.  int32
+ * results do not depend on b; fp32 results are the blocked method's with
+ * this b (every candidate is one IEEE addition, but phase 1 closes a b x b
+ * block in pivot order, so the last bits may differ between widths).
+ * Returns 0 for a bad dtype. */
 int32_t apsp_round_width(int64_t n, int32_t dtype);
+
+/* apsp_set_width64_max_n -- the largest n that apsp_solve and its variants
+ * solve in rounds of width 64 (0 disables them; at most
+ * APSP_WIDTH64_MAX_N_LIMIT).  Process-wide, for solves enqueued afterwards;
+ * no HIP call.  A solve split over apsp_solve_rounds calls must not change
+ * it between its calls.  Returns the previous value, or -1 (unchanged) for
+ * n < 0 or n > APSP_WIDTH64_MAX_N_LIMIT. */
+#define APSP_WIDTH64_MAX_N_LIMIT 8192
+int64_t apsp_set_width64_max_n(int64_t n);
 
 /*
  * apsp_solve_batched -- solve `count` independent int32 graphs together.

@@ -65,6 +65,7 @@ def _load() -> ctypes.CDLL:
         "apsp_round_width": ([i64, i32], i32),
         "apsp_batched_round_width": ([i64, i32], i32),
         "apsp_set_round_pair_threshold": ([i32], i32),
+        "apsp_set_width64_max_n": ([i64], i64),
         "apsp_solve_batched": ([vp, vp, i32, vp], i32),
         "apsp_solve_batched_ex": ([vp, vp, vp, i32, i32, vp], i32),
         "apsp_solve_batched_noalloc": ([vp, vp, vp, i32, i32, vp], i32),
@@ -165,6 +166,16 @@ def set_round_pair_threshold(rounds: int) -> int:
     prev = int(_LIB.apsp_set_round_pair_threshold(int(rounds)))
     if prev < 0:
         raise ValueError("the threshold is a number of rounds >= 2")
+    return prev
+
+
+def set_width64_max_n(n: int) -> int:
+    """Largest n solved in rounds of width 64 (process-wide; default 5120;
+    0 disables them); returns the previous value.  fp32 results follow the
+    blocked method at the width round_width(n) reports."""
+    prev = int(_LIB.apsp_set_width64_max_n(int(n)))
+    if prev < 0:
+        raise ValueError("the limit is a vertex count in [0, 8192]")
     return prev
 
 

@@ -77,8 +77,13 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
     return res;
 }
 
-int32_t apsp_round_width(int64_t, int32_t dtype) {
-    return bad_dtype(dtype) ? 0 : apsp::kRoundB;
+int32_t apsp_round_width(int64_t n, int32_t dtype) {
+    return bad_dtype(dtype) ? 0 : apsp::round_width(n);
+}
+
+int64_t apsp_set_width64_max_n(int64_t n) {
+    if (n < 0 || n > APSP_WIDTH64_MAX_N_LIMIT) return -1;
+    return apsp::set_width64_max_n(n);
 }
 
 int32_t apsp_set_round_pair_threshold(int32_t rounds) {

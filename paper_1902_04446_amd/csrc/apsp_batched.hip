@@ -68,11 +68,11 @@ __device__ __forceinline__ void batched_item64(uint32_t *D, int n, int64_t ld, b
     uint32_t acc[4][4];
     tile64::load64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
     if (CLOSE_ONLY) {
-        tile64::close64<Op>(acc, kw, L);
+        tile64::close64_pairs<Op>(acc, kw, L);
     } else {
         tile64::update64<Op>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
         if (I == r + 1 && J == r + 1)  // phase 1 of round r+1, fused
-            tile64::close64<Op>(acc, mr, L);
+            tile64::close64_pairs<Op>(acc, mr, L);
     }
     tile64::store64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
 }

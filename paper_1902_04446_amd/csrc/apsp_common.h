@@ -142,6 +142,20 @@ hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
 int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 int64_t num_rounds(int64_t n);
 
+// ---- width-64 rounds for small matrices (apsp_small.hip) --------------------
+// The single-graph solver's round width for an n-vertex matrix: 64 up to a
+// process-wide limit (set_width64_max_n), else kRoundB.
+int round_width(int64_t n);
+int64_t set_width64_max_n(int64_t n);
+int64_t num_rounds64(int64_t n);
+// Phase 1 of round r at width 64.
+hipError_t launch_phase1_64(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                            hipStream_t s);
+// A phase-2/3 tile set of round r at width 64 (kRest: block rows [lo, hi)).
+hipError_t launch_tile_set64(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int set,
+                             hipStream_t s, bool close_next_diag, const uint32_t *wmax,
+                             int64_t lo, int64_t hi);
+
 // ---- round pairs (apsp_pair.hip) -------------------------------------------
 // Copies of round panels, all with leading dimension ld = 128 q (q rounds):
 // row[s] holds a block row (its row k at offset k * ld); colT[s] a block

@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "apsp_tile.h"
+#include "apsp_tilemap.h"
 
 namespace apsp {
 
@@ -135,59 +136,11 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 // C = min(C, A (x) B) with A = D[i0.., K] and B = D[K, j0..]
 // (tile::minplus_tile; 8 x 8 registers per thread, k-paired min3).  MODE
 // selects the tile set of the launch (apsp_common.h); the workgroup -> tile
-// maps are bijections onto each set.
+// maps (apsp_tilemap.h) are bijections onto each set.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __device__ __forceinline__ void tile_of(int r, int q, int row_lo, int row_hi, int &I, int &J) {
-    if (MODE == kPanels) {
-        int tt = blockIdx.x;
-        if (tt < q - 1) {
-            I = r;
-            J = tt < r ? tt : tt + 1;
-        } else {
-            tt -= q - 1;
-            J = r;
-            I = tt < r ? tt : tt + 1;
-        }
-    } else if (MODE == kNext) {
-        // block row r+1 (every column but r), then block column r+1 (every
-        // row but r and r+1): the tiles the next round's phases 1 and 2 read
-        int tt = blockIdx.x;
-        if (tt < q - 1) {
-            I = r + 1;
-            J = tt < r ? tt : tt + 1;
-        } else {
-            tt -= q - 1;
-            J = r + 1;
-            I = tt < r ? tt : tt + 2;
-        }
-    } else {
-        // kAll: every block row/column but r.  kRest: the block rows in
-        // [row_lo, row_hi) but r and r+1, every block column but r and r+1.
-        // Workgroups are dealt round-robin to the 8 XCDs (wg % 8); give each
-        // XCD a contiguous range of tiles so tiles sharing panel blocks share
-        // that XCD's L2.
-        const int skip = (MODE == kRest) ? 2 : 1;
-        const int m = q - skip;
-        const int rows = (MODE == kRest)
-                             ? row_hi - row_lo - (r >= row_lo && r < row_hi ? 1 : 0) -
-                                   (r + 1 >= row_lo && r + 1 < row_hi ? 1 : 0)
-                             : m;
-        const int T = rows * m;
-        const int wg = blockIdx.x;
-        const int x = wg & 7, s = wg >> 3;
-        const int per = T >> 3, rem = T & 7;
-        const int tile = x * per + (x < rem ? x : rem) + s;
-        const int ti = tile / m, tj = tile - ti * m;
-        if (MODE == kRest) {
-            I = row_lo + ti;
-            if (r >= row_lo && I >= r) ++I;
-            if (r + 1 >= row_lo && I >= r + 1) ++I;
-        } else {
-            I = ti < r ? ti : ti + skip;
-        }
-        J = tj < r ? tj : tj + skip;
-    }
+    tilemap::tile_of<MODE>((int)blockIdx.x, r, q, row_lo, row_hi, I, J);
 }
 
 // NORM converts on load and store (OpI32F: int32 storage, fp32 arithmetic).
@@ -204,7 +157,7 @@ __device__ __forceinline__ void tile_update(uint32_t *D, int64_t ld, int64_t n, 
     tile::minplus_tile<Op, NORM>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
     // Phase 1 of round r+1, fused: the workgroup that just produced diagonal
     // block r+1 closes it in registers before storing it.
-    if (MODE == kNext && close_diag && I == r + 1 && J == r + 1)
+    if ((MODE == kNext || MODE == kAll) && close_diag && I == r + 1 && J == r + 1)
         tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
     tile::store_acc<Op>(acc, D, ld, i0, j0, mr, nc, vec);
 }
@@ -333,14 +286,7 @@ int64_t num_rounds(int64_t n) { return (n + TB - 1) / TB; }
 
 int64_t tile_count(int64_t n, int64_t r, int set) {
     const int64_t q = num_rounds(n);
-    if (r < 0 || r >= q) return 0;
-    switch (set) {
-    case kPanels: return 2 * (q - 1);
-    case kAll: return (q - 1) * (q - 1);
-    case kNext: return (r + 1 < q) ? 2 * q - 3 : 0;
-    case kRest: return (r + 1 < q) ? (q - 2) * (q - 2) : 0;
-    default: return 0;
-    }
+    return tilemap::tile_count(q, r, set, 0, q);
 }
 
 hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s) {
@@ -360,7 +306,7 @@ hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_
     if (count <= 0) return hipSuccess;
     const int q = (int)num_rounds(n);
     const int vec = aligned16(D, ld) ? 1 : 0;
-    const int close = (set == kNext && close_next_diag) ? 1 : 0;
+    const int close = ((set == kNext || set == kAll) && close_next_diag) ? 1 : 0;
     if (dtype == 0 && wmax)
         launch_tiles_i32(set, D, n, ld, (int)r, q, vec, close, 0, q, wmax, s, (unsigned)count);
     else if (dtype == 0)
@@ -382,10 +328,7 @@ hipError_t launch_wmax(const uint32_t *D, int64_t n, int64_t ld, uint32_t *wmax,
 }
 
 int64_t rest_rows_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
-    const int64_t q = num_rounds(n);
-    if (r < 0 || r + 1 >= q || lo >= hi) return 0;
-    const int64_t rows = hi - lo - (r >= lo && r < hi ? 1 : 0) - (r + 1 >= lo && r + 1 < hi ? 1 : 0);
-    return rows > 0 ? rows * (q - 2) : 0;
+    return tilemap::tile_count(num_rounds(n), r, kRest, lo, hi);
 }
 
 hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, int64_t lo,

@@ -56,6 +56,16 @@ constexpr int kBands = 2;
 #define APSP_MIN_BAND_ROUNDS 64
 #endif
 constexpr int64_t kMinBandRounds = APSP_MIN_BAND_ROUNDS;
+// Rounds of 64 from which the one-round lookahead is used.  Below it each
+// round is phase 2 then the whole phase 3 (with the next closure fused) on the
+// caller's stream: measured, the cross-stream events of the lookahead cost
+// more than its overlap up to 48 rounds (n = 2048: 1.05 ms without, 1.24 ms
+// with; n = 3072: 1.94 / 2.01), break even at 64 and win from 80 (n = 5120:
+// 5.89 / 5.63 ms).
+#ifndef APSP_W64_LOOKAHEAD_ROUNDS
+#define APSP_W64_LOOKAHEAD_ROUNDS 64
+#endif
+constexpr int64_t kW64LookaheadRounds = APSP_W64_LOOKAHEAD_ROUNDS;
 // From this many rounds on, phase 3 runs in round pairs (apsp_pair.hip):
 // one pass with k over two blocks reads and writes each tile once per two
 // rounds.  Below it the pair's longer chain of launches on the caller's
@@ -64,6 +74,14 @@ constexpr int64_t kMinBandRounds = APSP_MIN_BAND_ROUNDS;
 // (apsp_set_round_pair_threshold).
 constexpr int64_t kDefaultPairRounds = 72;
 std::atomic<int64_t> g_pair_rounds{kDefaultPairRounds};
+// Matrices of at most this many vertices run rounds of width 64
+// (apsp_small.hip): below it a solve is bound by the chain of dependent
+// launches, which 64-wide rounds shorten.  Measured (fp32 Swiss-roll kNN,
+// width 64 / 128): n = 256 0.13 / 0.26 ms, 1024 0.47 / 1.06, 4096 3.45 /
+// 4.59, 5120 5.63 / 5.91, 6144 9.34 / 8.41.  Settable per process
+// (apsp_set_width64_max_n).
+constexpr int64_t kDefaultWidth64MaxN = 5120;
+std::atomic<int64_t> g_w64_max_n{kDefaultWidth64MaxN};
 
 struct Helper {
     hipStream_t side[kBands] = {};
@@ -185,14 +203,19 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 
 hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0, int64_t r1,
                       bool prologue, hipStream_t s, PhaseTimes *times) {
-    const int64_t q = num_rounds(n);
+    // Round width: 64 for small matrices (apsp_small.hip), else 128.
+    const int b = round_width(n);
+    const bool w64 = b != kRoundB;
+    const int64_t q = (n + b - 1) / b;
     if (r1 > q) r1 = q;
     if (times)
         for (double &m : times->ms) m = 0.0;
     if (n <= 0 || r0 >= r1) return hipSuccess;
 
-    // Lookahead needs a round r+1 with a non-empty rest set.
-    const bool lookahead = q >= 3;
+    // Lookahead needs a round r+1 with a non-empty rest set; for a few
+    // rounds of 64 the rest set is a handful of tiles and the cross-stream
+    // events cost more than the overlap gains.
+    const bool lookahead = q >= (w64 ? kW64LookaheadRounds : 3);
     const int bands = q >= kMinBandRounds ? kBands : 1;
     hipError_t herr = hipSuccess;
     Helper *h = (lookahead || dtype == 0) ? helper_for(s, &herr) : nullptr;
@@ -203,8 +226,20 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
     // Pairs run on the helper streams, which exist from 3 rounds on (below
     // that a pair has no rest set anyway), whatever the threshold.
-    const bool pairs =
-        lookahead && q >= g_pair_rounds.load() && r1 - r0 >= 2 && ensure_copies(h, n, s);
+    const bool pairs = !w64 && lookahead && q >= g_pair_rounds.load() && r1 - r0 >= 2 &&
+                       ensure_copies(h, n, s);
+    // the phase launches at this width
+    auto phase1 = [&](int64_t r) {
+        return w64 ? launch_phase1_64(D, n, ld, dtype, r, s) : launch_phase1(D, n, ld, dtype, r, s);
+    };
+    auto tile_set = [&](int64_t r, int set, bool close_next) {
+        return w64 ? launch_tile_set64(D, n, ld, dtype, r, set, s, close_next, wmax, 0, q)
+                   : launch_tile_set(D, n, ld, dtype, r, set, s, close_next, wmax);
+    };
+    auto rest_rows = [&](int64_t r, int64_t lo, int64_t hi, hipStream_t st) {
+        return w64 ? launch_tile_set64(D, n, ld, dtype, r, kRest, st, false, wmax, lo, hi)
+                   : launch_rest_rows(D, n, ld, dtype, r, lo, hi, st, wmax);
+    };
 
     // Timing: spans of enqueued work on a stream, by category (the PhaseTimes
     // index: 1 phase 1, 2 phase 2, 7 phase 3 on the caller's stream, 5 the
@@ -267,11 +302,11 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     // A round's phase 1 + 2 on S (phase 1 unless an earlier launch fused it).
     auto phases12 = [&](int64_t r) {
         size_t sp = open(1, s);
-        if (!diag_closed) chk(launch_phase1(D, n, ld, dtype, r, s));
+        if (!diag_closed) chk(phase1(r));
         close(sp, s);
         diag_closed = false;
         sp = open(2, s);
-        chk(launch_tile_set(D, n, ld, dtype, r, kPanels, s, false, wmax));
+        chk(tile_set(r, kPanels, false));
         close(sp, s);
     };
 
@@ -306,7 +341,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 }
                 phases12(r);
                 const size_t sp = open(7, s);
-                chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
+                chk(tile_set(r, kAll, false));
                 close(sp, s);
                 ++r;
                 break;
@@ -381,7 +416,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 chk(hipEventRecord(h->p2_done, s));
                 wait_rest(s);
                 size_t sp = open(7, s);
-                chk(launch_tile_set(D, n, ld, dtype, r, kNext, s, fuse, wmax));
+                chk(tile_set(r, kNext, fuse));
                 close(sp, s);
                 diag_closed = fuse;
                 for (int g = 0; g < bands; ++g) {
@@ -400,18 +435,22 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                     band_range(g, lo, hi);
                     chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                     const size_t b = open(5, h->side[g]);
-                    chk(launch_rest_rows(D, n, ld, dtype, r, lo, hi, h->side[g], wmax));
+                    chk(rest_rows(r, lo, hi, h->side[g]));
                     close(b, h->side[g]);
                     chk(hipEventRecord(h->rest_done[g], h->side[g]));
                 }
                 rest_pending = true;
                 ++rest_launches;
             } else {
+                // whole phase 3 on S; its workgroup of diagonal block r+1
+                // closes it (phase 1 of round r+1) unless the call stops here
                 wait_rest(s);
                 rest_pending = false;
+                const bool fuse = r + 1 < r1;
                 const size_t sp = open(7, s);
-                chk(launch_tile_set(D, n, ld, dtype, r, kAll, s, false, wmax));
+                chk(tile_set(r, kAll, fuse));
                 close(sp, s);
+                diag_closed = fuse;
             }
         }
         wait_rest(s);
@@ -453,5 +492,9 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
 }
 
 int64_t set_pair_rounds(int64_t rounds) { return g_pair_rounds.exchange(rounds); }
+
+int round_width(int64_t n) { return n <= g_w64_max_n.load() ? 64 : kRoundB; }
+
+int64_t set_width64_max_n(int64_t n) { return g_w64_max_n.exchange(n); }
 
 }  // namespace apsp

@@ -196,5 +196,87 @@ __device__ __forceinline__ void close64(uint32_t (&acc)[4][4], int kw, Lds64 &L)
     }
 }
 
+// The same closure with one barrier per two pivots.  For pivots k, k+1 the
+// owners publish the rows and columns k and k+1 as they stand before pivot
+// k; every thread then forms, for its own rows i and columns j, the entries
+// pivot k gives column k+1 and row k+1,
+//     c'_i = min(d_i,k+1, d_ik + d_k,k+1)     r'_j = min(d_k+1,j, d_k+1,k + d_kj)
+// (the sequential loop's operations on those entries, so its bits; pivot k
+// changes neither row k nor column k, d_kk being 0), and applies both pivots
+// with one three-input minimum:
+//     d_ij = min3(d_ij, d_ik + d_kj, c'_i + r'_j).
+// Sequential Floyd-Warshall reaches min(min(d_ij, d_ik + d_kj), c'_i + r'_j)
+// from the same two sums; the minimum is exact, so the bits are the same.
+// Half the barriers of close64 for the same VALU work.  A trailing odd pivot
+// runs alone.  The LDS staging area of update64 is free during a closure and
+// holds the published rows and columns (double-buffered).
+template <class Op>
+__device__ __forceinline__ void close64_pairs(uint32_t (&acc)[4][4], int kw, Lds64 &L) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    uint32_t *buf = reinterpret_cast<uint32_t *>(&L.As[0][0]);  // [2][4][64]
+    int k = 0;
+    for (; k + 1 < kw; k += 2) {  // kw is uniform over the workgroup
+        uint32_t *b = buf + ((k >> 1) & 1) * 256;
+        uint32_t *r0 = b, *r1 = b + 64, *c0 = b + 128, *c1 = b + 192;
+        const int u = k & 3;  // k even: rows/columns k, k+1 are u, u+1 of one thread group
+        if (ty == (k >> 2)) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                r0[tx * 4 + e] = acc[u][e];
+                r1[tx * 4 + e] = acc[u + 1][e];
+            }
+        }
+        if (tx == (k >> 2)) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                c0[ty * 4 + m] = acc[m][u];
+                c1[ty * 4 + m] = acc[m][u + 1];
+            }
+        }
+        __syncthreads();
+        const uint32_t dk_k1 = r0[k + 1], dk1_k = r1[k];
+        uint32_t ck[4], ck1[4], rk[4], rk1[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            ck[m] = c0[ty * 4 + m];
+            ck1[m] = Op::min2(c1[ty * 4 + m], Op::add(ck[m], dk_k1));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rk[e] = r0[tx * 4 + e];
+            rk1[e] = Op::min2(r1[tx * 4 + e], Op::add(dk1_k, rk[e]));
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc[m][e] = Op::min3(acc[m][e], Op::add(ck[m], rk[e]), Op::add(ck1[m], rk1[e]));
+    }
+    if (k < kw) {  // the last pivot of an odd kw
+        uint32_t *b = buf + ((k >> 1) & 1) * 256;
+        uint32_t *r0 = b, *c0 = b + 128;
+        const int u = k & 3;
+        if (ty == (k >> 2)) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) r0[tx * 4 + e] = acc[u][e];
+        }
+        if (tx == (k >> 2)) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) c0[ty * 4 + m] = acc[m][u];
+        }
+        __syncthreads();
+        uint32_t ck[4], rk[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) ck[m] = c0[ty * 4 + m];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rk[e] = r0[tx * 4 + e];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[m][e] = Op::min2(acc[m][e], Op::add(ck[m], rk[e]));
+    }
+    __syncthreads();  // every read of the published rows done before the LDS is reused
+}
+
 }  // namespace tile64
 }  // namespace apsp

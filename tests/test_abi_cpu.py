@@ -174,10 +174,25 @@ def test_status_strings_and_widths(lib):
         s = lib.apsp_status_string(code)
         assert s and s.startswith(b"APSP")
     assert lib.apsp_status_string(99) == b"APSP: unknown status"
-    assert lib.apsp_round_width(100, 0) == 128 and lib.apsp_round_width(100, 1) == 128
+    assert lib.apsp_round_width(100, 0) == 64 and lib.apsp_round_width(5120, 1) == 64
+    assert lib.apsp_round_width(5121, 0) == 128 and lib.apsp_round_width(16384, 1) == 128
     assert lib.apsp_round_width(100, 5) == 0
     assert lib.apsp_batched_round_width(300, 0) == 128
     assert b"gfx950" in lib.apsp_version()
+
+
+def test_width64_limit_setter(lib):
+    """No HIP call: the width-64 limit is process-wide, in [0, 4096]."""
+    prev = lib.apsp_set_width64_max_n(300)
+    try:
+        assert prev >= 0
+        assert lib.apsp_round_width(300, 1) == 64 and lib.apsp_round_width(301, 1) == 128
+        assert lib.apsp_set_width64_max_n(-1) == -1
+        assert lib.apsp_set_width64_max_n(8193) == -1
+        assert lib.apsp_set_width64_max_n(0) == 300
+        assert lib.apsp_round_width(1, 0) == 128
+    finally:
+        lib.apsp_set_width64_max_n(prev)
 
 
 def test_round_pair_threshold_setter(lib):

@@ -122,7 +122,7 @@ def test_leading_dimension_and_alignment(apsp, dev, ld_extra, offset):
         if W.dtype == np.int32:
             assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8))
         else:
-            assert np.array_equal(got, oracle.blocked(W, 128))
+            assert np.array_equal(got, oracle.blocked(W, apsp.round_width(n)))
         # nothing outside the n x n view was written
         mask = torch.ones_like(buf, dtype=torch.bool)
         mask[offset:offset + n * (n + ld_extra)].view(n, n + ld_extra)[:, :n] = False
@@ -209,20 +209,30 @@ def test_resume_equals_full_solve(apsp, dev):
     assert np.array_equal(view2.cpu().numpy(), full)
 
 
-def test_profiled_equals_plain_and_is_deterministic(apsp, dev):
+@pytest.mark.parametrize("w64", [True, False])
+def test_profiled_equals_plain_and_is_deterministic(apsp, dev, w64):
+    """Profiled and plain solves agree bit for bit and repeat exactly: in 11
+    rounds of 64 (each round's whole phase 3 on the caller's stream) and in
+    6 rounds of 128 (the rest of phase 3 beside the next round's phases)."""
     import torch
 
     n = 700
     W, _ = _swiss(n, 33)
-    a = _solve(apsp, W, dev)
-    view, _ = _to_dev(W, dev)
-    t = apsp.solve_profiled(view)
-    assert np.array_equal(view.cpu().numpy(), a)
-    assert all(t[k] >= 0 for k in t) and t["total"] > 0 and t["phase3"] > 0
-    assert t["phase3_rest_launches"] == apsp.num_rounds(n) - 1
-    b = _solve(apsp, W, dev)
-    assert a.tobytes() == b.tobytes()
-    torch.cuda.synchronize()
+    prev = apsp.set_width64_max_n(5120 if w64 else 0)
+    try:
+        a = _solve(apsp, W, dev)
+        view, _ = _to_dev(W, dev)
+        t = apsp.solve_profiled(view)
+        assert np.array_equal(view.cpu().numpy(), a)
+        assert all(t[k] >= 0 for k in t) and t["total"] > 0 and t["phase3"] > 0
+        q = apsp.num_rounds(n)
+        assert q == (11 if w64 else 6)
+        assert t["phase3_rest_launches"] == (0 if w64 else q - 1)
+        b = _solve(apsp, W, dev)
+        assert a.tobytes() == b.tobytes()
+        torch.cuda.synchronize()
+    finally:
+        apsp.set_width64_max_n(prev)
 
 
 def test_validate(apsp, dev):
@@ -332,7 +342,8 @@ def test_int32_slices_switch_pipes(apsp, dev):
         torch.cuda.synchronize()
         part = view.cpu().numpy()
         if r0 + 1 < q:
-            ref = np.minimum(oracle.fw_steps(oracle.prepare(W), 0, (r0 + 1) * 128, threads=4),
+            ref = np.minimum(oracle.fw_steps(oracle.prepare(W), 0, (r0 + 1) * apsp.round_width(n),
+                                              threads=4),
                              INF)
             assert np.array_equal(part.astype(np.int64), ref), r0
     fin = part[part < INF]
@@ -394,7 +405,15 @@ def _banded_ragged(apsp, dev, whi, n=8300, rounds=65):
 # the blocked model bit for bit.
 
 @pytest.fixture
-def pairs_from_8(apsp):
+def width128(apsp):
+    """Every n in rounds of 128 (round pairs exist only at that width)."""
+    prev = apsp.set_width64_max_n(0)
+    yield
+    apsp.set_width64_max_n(prev)
+
+
+@pytest.fixture
+def pairs_from_8(apsp, width128):
     prev = apsp.set_round_pair_threshold(8)
     yield
     apsp.set_round_pair_threshold(prev)
@@ -494,7 +513,7 @@ def test_pair_schedule_random_slices(apsp, dev, pairs_from_8):
 
 
 @pytest.mark.parametrize("n", [129, 256, 300, 384])
-def test_pair_threshold_two_small_matrices(apsp, dev, n):
+def test_pair_threshold_two_small_matrices(apsp, dev, width128, n):
     """Threshold 2 on matrices of 2 and 3 rounds, int32 and fp32, in one call
     and in calls of two rounds.  Pairs need the helper streams, which fp32
     matrices of 2 rounds do not get: those run single rounds (a pair would
@@ -577,6 +596,61 @@ def test_pair_schedule_profiled(apsp, dev, pairs_from_8):
         assert np.array_equal(_solve(apsp, W, dev), a)
     finally:
         apsp.set_round_pair_threshold(prev)
+
+
+# --------------------------------------------------- width-64 rounds (small n)
+
+@pytest.mark.parametrize("n", [65, 129, 200, 257, 640, 1000, 1024])
+def test_width64_rounds(apsp, dev, n):
+    """Small matrices run rounds of width 64 (with the one-round lookahead from
+    3 rounds on): int32 equals the oracle and fp32 the blocked model at width
+    64 bit for bit (and fp64 Floyd-Warshall within 1e-5); an int32 solve cut
+    into slices passes through Floyd-Warshall's state after 64 r pivots."""
+    import torch
+
+    assert apsp.round_width(n) == 64
+    Wi, _ = _er(n, min(1.0, 4.0 / n), 3100 + n, 1, 1000)
+    Wf, _ = _swiss(n, 3200 + n)
+    assert np.array_equal(_solve(apsp, Wi, dev).astype(np.int64), oracle.fw(Wi, threads=8))
+    got = _solve(apsp, Wf, dev)
+    assert np.array_equal(got, oracle.blocked(Wf, 64))
+    _assert_f32_close(got, oracle.fw(Wf, threads=8))
+    q = apsp.num_rounds(n)
+    assert q == -(-n // 64)
+    cuts = sorted({0, 1, q // 2, q - 1, q})
+    view, _ = _to_dev(Wi, dev, ld=n + 5)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        apsp.solve_rounds(view, a, b)
+        torch.cuda.synchronize()
+        ref = oracle.fw_steps(oracle.prepare(Wi), 0, min(b * 64, n), threads=8)
+        assert np.array_equal(view.cpu().numpy().astype(np.int64), np.minimum(ref, INF)), b
+
+
+def test_width64_bands(apsp, dev):
+    """With the limit raised to 4096, n = 4050 takes 64 rounds of 64: the rest
+    of phase 3 then runs in two bands of block rows.  int32 (both pipes)
+    equals the oracle; fp32 matches fp64 Dijkstra on sampled rows."""
+    import torch
+
+    n = 4050
+    prev = apsp.set_width64_max_n(4096)
+    try:
+        assert apsp.num_rounds(n) == 64
+        for whi in (100, 1 << 20):
+            Wi, _ = _er(n, 6.0 / n, 3300 + whi, 1, whi)
+            assert np.array_equal(_solve(apsp, Wi, dev).astype(np.int64),
+                                  oracle.fw(Wi, threads=16)), whi
+        Wf, (u, v, w) = _swiss(n, 3400)
+        view, _ = _to_dev(Wf, dev)
+        t = apsp.solve_profiled(view)
+        assert t["phase3_rest_launches"] == 63
+        got = view.cpu().numpy()
+        rows = gg.rng_for(gg.CFG_TEST, 3401).choice(n, size=24, replace=False)
+        csr = oracle.csr_from_dense(Wf)
+        ref = oracle.dijkstra(csr, n, rows, threads=8)
+        _assert_f32_close(got[rows], ref)
+    finally:
+        apsp.set_width64_max_n(prev)
 
 
 # --------------------------------------------------------------- batched
@@ -957,7 +1031,8 @@ def test_fp32_nonzero_diagonal(apsp, dev, n):
     import torch
 
     W = _f32_with_diagonal(n, 9700 + n)
-    ref = oracle.blocked(W, 128)
+    ref = oracle.blocked(W, apsp.round_width(n))
+    ref128 = oracle.blocked(W, 128)
     ref64 = oracle.fw(W)
     assert (np.diag(ref) == 0).all()
     # apsp_solve
@@ -975,7 +1050,7 @@ def test_fp32_nonzero_diagonal(apsp, dev, n):
     view, _ = _to_dev(W, dev, ld=n + 2)
     apsp.solve_symmetric(view)
     torch.cuda.synchronize()
-    assert np.array_equal(view.cpu().numpy(), ref), "apsp_solve_symmetric"
+    assert np.array_equal(view.cpu().numpy(), ref128), "apsp_solve_symmetric"
     # batched, one-shot call and both forced widths
     views = [_to_dev(W, dev)[0] for _ in range(3)]
     apsp.solve_batched([views[0]])
@@ -986,6 +1061,6 @@ def test_fp32_nonzero_diagonal(apsp, dev, n):
     assert np.array_equal(views[0].cpu().numpy(),
                           oracle.blocked(W, apsp.batched_round_width(n, apsp.APSP_F32)))
     assert np.array_equal(views[1].cpu().numpy(), oracle.blocked(W, 64)), "batched width 64"
-    assert np.array_equal(views[2].cpu().numpy(), ref), "batched width 128"
+    assert np.array_equal(views[2].cpu().numpy(), ref128), "batched width 128"
     for p in plans:
         p.close()

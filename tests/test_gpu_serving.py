@@ -63,7 +63,7 @@ def test_mix_equals_alone(apsp, slice_rounds):
         if r.n <= 300:
             u, v, w = r.payload
             W = gg.dense_from_edges(r.n, u, v, w, np.float32)
-            assert np.array_equal(r.result.cpu().numpy(), oracle.blocked(W, 128))
+            assert np.array_equal(r.result.cpu().numpy(), oracle.blocked(W, apsp.round_width(W.shape[0])))
 
 
 @pytest.mark.parametrize("slice_rounds", [3, 4])
@@ -81,16 +81,20 @@ def test_mix_equals_alone_round_pairs(apsp, slice_rounds):
     reqs = _requests(sizes, 850 + slice_rounds)
     backend = GpuBackend(dev, slots=3, keep_results=True)
     srv = ApspServer(backend, hbm_budget=1 << 30, slots=3, slice_rounds=slice_rounds)
-    prev = apsp.set_round_pair_threshold(2)
+    prev_w = apsp.set_width64_max_n(0)  # round pairs run at width 128
     try:
-        stats = srv.run(reqs, realtime=False)
-        torch.cuda.synchronize()
+        prev = apsp.set_round_pair_threshold(2)
+        try:
+            stats = srv.run(reqs, realtime=False)
+            torch.cuda.synchronize()
+        finally:
+            apsp.set_round_pair_threshold(prev)
+        assert stats["done"] == len(sizes)
+        for r in reqs:  # alone: single rounds, at the same width
+            assert r.status == "done"
+            assert torch.equal(r.result, _alone(apsp, r, dev)), r.n
     finally:
-        apsp.set_round_pair_threshold(prev)
-    assert stats["done"] == len(sizes)
-    for r in reqs:
-        assert r.status == "done"
-        assert torch.equal(r.result, _alone(apsp, r, dev)), r.n
+        apsp.set_width64_max_n(prev_w)
 
 
 def test_admission_under_small_budget(apsp):
