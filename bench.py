@@ -265,7 +265,12 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
     plan = apsp.BatchPlan(work)
     t_batched = timed(plan.run)
     same = same and same_as(ref)
-    t_oneshot = timed(lambda: apsp.solve_batched(work))
+    t0 = time.perf_counter()
+    args = apsp.BatchArgs(work)  # the list marshalled once (Python work, ~1 us per matrix)
+    t_marshal = time.perf_counter() - t0
+    t_oneshot = timed(lambda: apsp.solve_batched(args))
+    same = same and same_as(ref)
+    t_noalloc = timed(lambda: apsp.solve_batched_noalloc(args))
     same = same and same_as(ref)
     info = plan.info()
     plan.close()
@@ -280,7 +285,8 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
         same = same and same_as(ref)
     log(f"batched: tuned plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches); "
         f"width 128 only {fixed[128][0] * 1e3:.2f} ms, width 64 only {fixed[64][0] * 1e3:.2f} ms; "
-        f"one-shot call {t_oneshot * 1e3:.2f} ms, per-graph loop {t_loop * 1e3:.2f} ms, "
+        f"one-shot call {t_oneshot * 1e3:.2f} ms, allocation-free call {t_noalloc * 1e3:.2f} ms "
+        f"(marshalling the list {t_marshal * 1e3:.2f} ms), per-graph loop {t_loop * 1e3:.2f} ms, "
         f"identical={same}")
     return {"workload": f"{count} ER graphs, n log-uniform [32,512], p=8/n, int32 U{{1..1000}}; "
                         "row length rounded up to 4 elements",
@@ -291,6 +297,8 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
             "width128_only_ms": round(fixed[128][0] * 1e3, 3),
             "width64_only_ms": round(fixed[64][0] * 1e3, 3),
             "oneshot_call_ms": round(t_oneshot * 1e3, 3),
+            "noalloc_call_ms": round(t_noalloc * 1e3, 3),
+            "python_marshal_ms": round(t_marshal * 1e3, 3),
             "plain_loop_ms": round(t_loop * 1e3, 3) if loop_too else None,
             "batched_T_cell_updates_per_s": round(sum_n3 / t_batched / 1e12, 3),
             "plain_loop_T_cell_updates_per_s":

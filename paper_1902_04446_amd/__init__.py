@@ -16,7 +16,7 @@ import os
 __all__ = [
     "APSP_I32", "APSP_F32", "INF_I32", "ApspError", "lib_path", "library",
     "solve", "solve_profiled", "solve_rounds", "solve_batched", "solve_batched_noalloc",
-    "BatchPlan", "validate",
+    "BatchArgs", "BatchPlan", "validate",
     "minplus", "solve_squaring", "squarings", "solve_symmetric",
     "round_width", "batched_round_width", "num_rounds", "version",
     "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
@@ -265,34 +265,44 @@ def _batch_arrays(mats):
     return ptrs, ns, lds, dt, dev
 
 
-def solve_batched(mats, stream=None):
-    """Solve a list of independent square matrices (all int32, or all float32) together."""
+class BatchArgs:
+    """The host arrays (pointers, sizes, leading dimensions) of a batch of
+    device matrices, marshalled once.  solve_batched / solve_batched_noalloc
+    accept it in place of the list, so a caller that solves the same buffers
+    repeatedly pays the per-tensor Python work once (about 1 us per matrix).
+    It refers to the matrices' memory: keep ``mats`` alive while it is used."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        self.ptrs, self.ns, self.lds, self.dtype, self.device = _batch_arrays(self.mats)
+
+    def __len__(self):
+        return len(self.mats)
+
+
+def _batch_call(fn, name, mats, stream):
     import torch
 
-    mats = list(mats)
-    if not mats:
-        return mats
-    ptrs, ns, lds, dt, dev = _batch_arrays(mats)
-    with torch.cuda.device(dev):
-        _check(_LIB.apsp_solve_batched_ex(ptrs, ns, lds, len(mats), dt, _stream(stream)),
-               "apsp_solve_batched_ex")
-    return mats
+    args = mats if isinstance(mats, BatchArgs) else BatchArgs(mats)
+    if len(args) == 0:
+        return args.mats
+    with torch.cuda.device(args.device):
+        _check(fn(args.ptrs, args.ns, args.lds, len(args), args.dtype, _stream(stream)), name)
+    return args.mats
+
+
+def solve_batched(mats, stream=None):
+    """Solve a list of independent square matrices (all int32, or all float32)
+    together (or a BatchArgs of them)."""
+    return _batch_call(_LIB.apsp_solve_batched_ex, "apsp_solve_batched_ex", mats, stream)
 
 
 def solve_batched_noalloc(mats, stream=None):
     """solve_batched without any device allocation: the tables go to the
     library's fixed per-GPU workspace (apsp_solve_batched_noalloc; calls that
     overlap on one GPU race on it)."""
-    import torch
-
-    mats = list(mats)
-    if not mats:
-        return mats
-    ptrs, ns, lds, dt, dev = _batch_arrays(mats)
-    with torch.cuda.device(dev):
-        _check(_LIB.apsp_solve_batched_noalloc(ptrs, ns, lds, len(mats), dt, _stream(stream)),
-               "apsp_solve_batched_noalloc")
-    return mats
+    return _batch_call(_LIB.apsp_solve_batched_noalloc, "apsp_solve_batched_noalloc", mats,
+                       stream)
 
 
 class BatchPlan:

@@ -214,66 +214,59 @@ template <class Op>
 __device__ __forceinline__ void close64_pairs(uint32_t (&acc)[4][4], int kw, Lds64 &L) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     uint32_t *buf = reinterpret_cast<uint32_t *>(&L.As[0][0]);  // [2][4][64]
-    int k = 0;
-    for (; k + 1 < kw; k += 2) {  // kw is uniform over the workgroup
-        uint32_t *b = buf + ((k >> 1) & 1) * 256;
-        uint32_t *r0 = b, *r1 = b + 64, *c0 = b + 128, *c1 = b + 192;
-        const int u = k & 3;  // k even: rows/columns k, k+1 are u, u+1 of one thread group
-        if (ty == (k >> 2)) {
+    // pivots k = 4 kq + u, u unrolled: the register row/column u of a pivot is
+    // a compile-time index
+    for (int kq = 0; kq < 16; ++kq) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                r0[tx * 4 + e] = acc[u][e];
-                r1[tx * 4 + e] = acc[u + 1][e];
+        for (int u = 0; u < 4; u += 2) {
+            const int k = kq * 4 + u;
+            if (k < kw) {  // uniform over the workgroup
+                const bool pair = k + 1 < kw;
+                uint32_t *b = buf + ((k >> 1) & 1) * 256;
+                uint32_t *r0 = b, *r1 = b + 64, *c0 = b + 128, *c1 = b + 192;
+                if (ty == kq) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        r0[tx * 4 + e] = acc[u][e];
+                        r1[tx * 4 + e] = acc[u + 1][e];
+                    }
+                }
+                if (tx == kq) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        c0[ty * 4 + m] = acc[m][u];
+                        c1[ty * 4 + m] = acc[m][u + 1];
+                    }
+                }
+                __syncthreads();
+                uint32_t ck[4], ck1[4], rk[4], rk1[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) ck[m] = c0[ty * 4 + m];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) rk[e] = r0[tx * 4 + e];
+                if (pair) {
+                    const uint32_t dk_k1 = r0[k + 1], dk1_k = r1[k];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        ck1[m] = Op::min2(c1[ty * 4 + m], Op::add(ck[m], dk_k1));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rk1[e] = Op::min2(r1[tx * 4 + e], Op::add(dk1_k, rk[e]));
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[m][e] = Op::min3(acc[m][e], Op::add(ck[m], rk[e]),
+                                                 Op::add(ck1[m], rk1[e]));
+                } else {  // the last pivot of an odd kw
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[m][e] = Op::min2(acc[m][e], Op::add(ck[m], rk[e]));
+                }
             }
         }
-        if (tx == (k >> 2)) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                c0[ty * 4 + m] = acc[m][u];
-                c1[ty * 4 + m] = acc[m][u + 1];
-            }
-        }
-        __syncthreads();
-        const uint32_t dk_k1 = r0[k + 1], dk1_k = r1[k];
-        uint32_t ck[4], ck1[4], rk[4], rk1[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            ck[m] = c0[ty * 4 + m];
-            ck1[m] = Op::min2(c1[ty * 4 + m], Op::add(ck[m], dk_k1));
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            rk[e] = r0[tx * 4 + e];
-            rk1[e] = Op::min2(r1[tx * 4 + e], Op::add(dk1_k, rk[e]));
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                acc[m][e] = Op::min3(acc[m][e], Op::add(ck[m], rk[e]), Op::add(ck1[m], rk1[e]));
-    }
-    if (k < kw) {  // the last pivot of an odd kw
-        uint32_t *b = buf + ((k >> 1) & 1) * 256;
-        uint32_t *r0 = b, *c0 = b + 128;
-        const int u = k & 3;
-        if (ty == (k >> 2)) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) r0[tx * 4 + e] = acc[u][e];
-        }
-        if (tx == (k >> 2)) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) c0[ty * 4 + m] = acc[m][u];
-        }
-        __syncthreads();
-        uint32_t ck[4], rk[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) ck[m] = c0[ty * 4 + m];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rk[e] = r0[tx * 4 + e];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[m][e] = Op::min2(acc[m][e], Op::add(ck[m], rk[e]));
     }
     __syncthreads();  // every read of the published rows done before the LDS is reused
 }
