@@ -307,65 +307,121 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
             "bit_identical": bool(same)}
 
 
-def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2)) -> dict:
+# the host policy measured best for p99 at 0.8 C (2000 requests per run):
+# first come first served, n = 8192 requests one at a time beside the rest
+# (p99 70.9 ms; round-robin 73.5, SRPT 74.1, one request >= 4096 at a time
+# 110-141 ms)
+SERVING_POLICY = {"slots": 4, "slice_rounds": 8, "inflight": 2, "policy": "fifo",
+                  "max_running": None, "large_n": 8192, "max_large": 1}
+
+
+def bench_serving(apsp, torch, dev, count: int, loads=(0.5, 0.8, 1.2), policy=None,
+                  warmup_frac: float = 0.1, capacity=None) -> dict:
     """Poisson stream of APSP requests, n in {256, 1024, 4096, 8192} with
     probabilities {.4, .3, .2, .1}, each a seeded Swiss-roll kNN graph (k=10,
     fp32).  Capacity C = requests per second of back-to-back plain solves of
-    the same requests on one stream; the server then runs at the given
-    fractions of C and reports p50 / p99 latency and cell updates per second.
+    the same kind of requests on one stream; the server then runs `count`
+    requests at each given fraction of C, the first `warmup_frac` of them
+    left out of the latency figures, and reports p50 / p99 latency (overall
+    and per size) and cell updates per second.  The lone solve time of each
+    size is measured beside it.
     """
     import numpy as np
 
     import graphgen as gg
     from paper_1902_04446_amd.serving import ApspServer, GpuBackend, Request
 
+    pol = dict(SERVING_POLICY, **(policy or {}))
     per_size = 3
     log("serving: generating the request pool")
     pool = {n: [gg.swiss_roll_knn(n, gg.CFG_SERVING, 10 * n + k) for k in range(per_size)]
             for n in gg.SERVING_SIZES}
 
-    def make(qps, item):
-        arr, ns = gg.serving_requests(count, qps, item=item)
+    def make(qps, item, cnt=count):
+        arr, ns = gg.serving_requests(cnt, qps, item=item)
         return [Request(rid=i, n=int(n), arrival=float(a), payload=pool[int(n)][i % per_size])
                 for i, (a, n) in enumerate(zip(arr, ns))]
 
-    # capacity: the same kind of requests, one after another, plain solves
-    probe = make(1.0, 0)
+    # lone solve time of each size (matrix resident, one plain solve)
+    lone = {}
+    for n in gg.SERVING_SIZES:
+        u, v, w = pool[n][0]
+        P = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+        X = torch.empty_like(P)
+        ts = []
+        for _ in range(6):
+            X.copy_(P)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            apsp.solve(X)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        lone[str(n)] = round(sorted(ts[1:])[2] * 1e3, 3)
+        del P, X
+    log(f"serving: lone solve ms {lone}")
+
+    # capacity: the same kind of requests, one after another, plain solves on
+    # one stream; the median of three timed passes after an untimed one over
+    # 300 of them
+    probe = make(1.0, 0, min(count, 500))
     backend = GpuBackend(dev, slots=1, keep_results=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in probe:
-        D = backend.alloc(r, 0)
-        backend.load(D, r, 0)
-        with torch.cuda.stream(backend.streams[0]):
-            apsp.solve(D)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+
+    def plain(reqs):
+        for r in reqs:
+            D = backend.alloc(r, 0)
+            backend.load(D, r, 0)
+            apsp.solve(D, stream=backend.streams[0])
+
+    plain(probe[:300])
+    passes = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain(probe)
+        torch.cuda.synchronize()
+        passes.append(time.perf_counter() - t0)
+    backend.close()
+    t_plain = sorted(passes)[1]
     cap = len(probe) / t_plain
     work = float(sum(float(r.n) ** 3 for r in probe))
     log(f"serving: plain back-to-back {len(probe)} requests in {t_plain:.3f} s "
         f"-> capacity {cap:.1f} req/s, {work / t_plain / 1e12:.2f} T cell-updates/s")
+    if capacity is not None:  # a capacity measured earlier (policy sweeps)
+        cap = float(capacity)
     runs = []
+    warm = int(round(warmup_frac * count))
     for k, f in enumerate(loads):
         qps = f * cap
         reqs = make(qps, k + 1)
-        backend = GpuBackend(dev, slots=4, keep_results=False)
-        srv = ApspServer(backend, hbm_budget=8 << 30, slots=4, slice_rounds=8, inflight=2)
+        backend = GpuBackend(dev, slots=pol["slots"], keep_results=False)
+        srv = ApspServer(backend, hbm_budget=8 << 30, slots=pol["slots"],
+                         slice_rounds=pol["slice_rounds"], inflight=pol["inflight"],
+                         policy=pol["policy"], max_running=pol["max_running"],
+                         large_n=pol["large_n"], max_large=pol["max_large"], warmup=warm)
         st = srv.run(reqs, realtime=True)
+        backend.close()
         st["load"] = f
         st["qps"] = round(qps, 2)
         for key in ("p50_ms", "p99_ms", "mean_ms"):
             st[key] = round(st[key], 3) if st[key] is not None else None
+        for v in st["per_size"].values():
+            for key in ("p50_ms", "p99_ms", "max_ms"):
+                v[key] = round(v[key], 3)
+        st["p99_over_lone_8192"] = round(st["p99_ms"] / lone["8192"], 3) if st["p99_ms"] else None
         st["T_cell_updates_per_s"] = round(st.pop("cell_updates_per_s") / 1e12, 3)
         st["makespan_s"] = round(st["makespan_s"], 3)
         log(f"serving: load {f:.1f}C ({qps:.0f} req/s): p50 {st['p50_ms']} ms, "
-            f"p99 {st['p99_ms']} ms, {st['T_cell_updates_per_s']} T cell-updates/s")
+            f"p99 {st['p99_ms']} ms ({st['p99_over_lone_8192']} x lone 8192), "
+            f"{st['T_cell_updates_per_s']} T cell-updates/s; per size "
+            + ", ".join(f"{n}: {v['p50_ms']}/{v['p99_ms']}" for n, v in st["per_size"].items()))
         runs.append(st)
     return {"workload": "Poisson arrivals, n in {256,1024,4096,8192} w.p. {.4,.3,.2,.1}, "
                         "Swiss-roll kNN fp32", "requests_per_run": count,
-            "plain_capacity_req_per_s": round(cap, 2),
+            "warmup_excluded": warm, "lone_solve_ms": lone,
+            "plain_capacity_req_per_s": round(cap, 2), "capacity_probe_requests": len(probe),
+            "capacity_probe_passes_s": [round(x, 3) for x in passes],
             "plain_T_cell_updates_per_s": round(work / t_plain / 1e12, 3),
-            "slots": 4, "slice_rounds": 8, "hbm_budget_GiB": 8, "runs": runs}
+            "policy": pol, "hbm_budget_GiB": 8, "runs": runs}
 
 
 def bench_variants(apsp, torch, dev, pristine, work, n: int, b: int) -> dict:
@@ -624,8 +680,8 @@ def main() -> int:
                     help="graphs in the batched-vs-plain comparison (0 disables it)")
     ap.add_argument("--variants", type=int, default=1,
                     help="measure the symmetric, product and squaring solvers (0 disables)")
-    ap.add_argument("--serving", type=int, default=300,
-                    help="requests per serving run (0 disables the serving section)")
+    ap.add_argument("--serving", type=int, default=2000,
+                    help="requests per serving load level (0 disables the serving section)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
     ap.add_argument("--batched-loop", type=int, default=1,

@@ -75,7 +75,8 @@ enum {
  * Rounds are 64 wide up to n = 5120 and 128 wide above (apsp_round_width).
  * From 3 rounds on (64 rounds of width 64) the phases of round r+1 overlap the bulk of round r's phase 3
  * on library-owned helper streams (one set per device and caller stream,
- * created on first use and kept; from 64 rounds up that phase 3 runs as two
+ * created on first use and kept until apsp_release_stream_state; from 64
+ * rounds up that phase 3 runs as two
  * bands of block rows on two of them); the call makes `stream` wait for that
  * work, so stream order is preserved.  int32 matrices are first scanned for
  * their largest finite entry w; when 2 (n-1) w < 2^24 every sum the method
@@ -114,6 +115,37 @@ int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *strea
  * Returns the previous threshold, or -1 (unchanged) when rounds < 2.
  */
 int32_t apsp_set_round_pair_threshold(int32_t rounds);
+
+/*
+ * Per-stream state.  apsp_solve, apsp_solve_rounds and apsp_solve_profiled
+ * keep, per (device, caller stream), the state apsp_solve describes: two
+ * helper streams, three events, the 256-byte scan word and, once a solve ran
+ * round pairs, the panel copies.  int32 solves and solves long enough for the
+ * lookahead create it; it lives until released here or the process ends.
+ *
+ * apsp_stream_state_bytes -- device bytes of that state after a full solve
+ * of an n-vertex `dtype` matrix on a stream without state: 0 when such a
+ * solve creates none, else 256 plus the copies when it runs round pairs (at
+ * the current thresholds).  A stream's copies grow to its largest solve and
+ * never shrink.  No HIP call.  Returns -1 for a bad dtype or n out of range.
+ *
+ * apsp_stream_state_count -- how many (device, stream) states the process
+ * holds.  No HIP call.
+ *
+ * apsp_release_stream_state -- release the state of `stream` (NULL = the
+ * default stream) on the current device: blocks until all work enqueued on
+ * `stream` and on its helper streams has finished, then destroys the helper
+ * streams and events and frees the word and the copies.  A later solve on the
+ * stream creates them again.  Call it before destroying a stream the library
+ * solved on (a new stream may get the old handle) and when a stream is done
+ * with large solves; it must not run concurrently with a solve enqueued on
+ * the same stream from another thread.  Returns APSP_OK (also when the stream
+ * has no state) or APSP_ERR_DEVICE (a synchronisation failed; the state is
+ * kept).
+ */
+int64_t apsp_stream_state_bytes(int64_t n, int32_t dtype);
+int64_t apsp_stream_state_count(void);
+int32_t apsp_release_stream_state(void *stream);
 
 /*
  * apsp_solve_rounds -- run rounds r0 .. r1-1 of the blocked method only

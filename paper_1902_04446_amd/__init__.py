@@ -20,7 +20,8 @@ __all__ = [
     "minplus", "solve_squaring", "squarings", "solve_symmetric",
     "round_width", "batched_round_width", "num_rounds", "version",
     "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
-    "batched_autotune_batch",
+    "batched_autotune_batch", "set_round_pair_threshold", "set_width64_max_n",
+    "stream_state_bytes", "stream_state_count", "release_stream_state",
 ]
 
 APSP_I32 = 0
@@ -66,6 +67,9 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_round_width": ([i64, i32], i32),
         "apsp_set_round_pair_threshold": ([i32], i32),
         "apsp_set_width64_max_n": ([i64], i64),
+        "apsp_stream_state_bytes": ([i64, i32], i64),
+        "apsp_stream_state_count": ([], i64),
+        "apsp_release_stream_state": ([vp], i32),
         "apsp_solve_batched": ([vp, vp, i32, vp], i32),
         "apsp_solve_batched_ex": ([vp, vp, vp, i32, i32, vp], i32),
         "apsp_solve_batched_noalloc": ([vp, vp, vp, i32, i32, vp], i32),
@@ -177,6 +181,32 @@ def set_width64_max_n(n: int) -> int:
     if prev < 0:
         raise ValueError("the limit is a vertex count in [0, 8192]")
     return prev
+
+
+def stream_state_bytes(n: int, dtype: int = APSP_F32) -> int:
+    """Device bytes of the per-stream state a full solve of an n-vertex
+    matrix creates on a stream without state (0 if it creates none)."""
+    v = int(_LIB.apsp_stream_state_bytes(int(n), int(dtype)))
+    if v < 0:
+        raise ValueError("bad dtype or vertex count")
+    return v
+
+
+def stream_state_count() -> int:
+    """How many (device, stream) solver states the process holds."""
+    return int(_LIB.apsp_stream_state_count())
+
+
+def release_stream_state(stream=None, device=None):
+    """Release the solver state kept for ``stream`` (default: the current
+    stream) on ``device``: waits for that stream's work, then frees its helper
+    streams and memory.  Call it before dropping a stream solves ran on."""
+    import torch
+
+    dev = torch.device(device) if device is not None else (
+        stream.device if stream is not None else torch.device("cuda", torch.cuda.current_device()))
+    with torch.cuda.device(dev):
+        _check(_LIB.apsp_release_stream_state(_stream(stream)), "apsp_release_stream_state")
 
 
 def round_width(n: int = 0, dtype: int = APSP_F32) -> int:

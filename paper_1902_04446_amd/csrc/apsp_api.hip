@@ -86,6 +86,19 @@ int64_t apsp_set_width64_max_n(int64_t n) {
     return apsp::set_width64_max_n(n);
 }
 
+int64_t apsp_stream_state_bytes(int64_t n, int32_t dtype) {
+    if (bad_dtype(dtype) || n < 0 || n >= kMaxN) return -1;
+    return apsp::stream_state_bytes(n, dtype);
+}
+
+int64_t apsp_stream_state_count(void) { return apsp::stream_state_count(); }
+
+int32_t apsp_release_stream_state(void *stream) {
+    return apsp::release_stream_state(reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+               ? APSP_OK
+               : APSP_ERR_DEVICE;
+}
+
 int32_t apsp_set_round_pair_threshold(int32_t rounds) {
     if (rounds < 2) return -1;
     return (int32_t)apsp::set_pair_rounds(rounds);

@@ -266,5 +266,11 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                       bool prologue, hipStream_t s, PhaseTimes *times);
 // Rounds from which run_rounds uses round pairs; returns the previous value.
 int64_t set_pair_rounds(int64_t rounds);
+// Per-(device, caller stream) state of run_rounds: its device bytes after a
+// full solve of n on a fresh stream, how many states exist, and releasing the
+// state of `s` on the current device (waits for its work first).
+int64_t stream_state_bytes(int64_t n, int dtype);
+int64_t stream_state_count();
+hipError_t release_stream_state(hipStream_t s);
 
 }  // namespace apsp

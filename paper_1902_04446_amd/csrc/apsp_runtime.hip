@@ -175,6 +175,33 @@ Helper *helper_for(hipStream_t s, hipError_t *err) {
     return h;
 }
 
+// Destroy a helper's streams and events and free its device memory (its
+// work must have finished).
+void destroy_helper(Helper *h) {
+    for (hipStream_t x : h->side)
+        if (x) (void)hipStreamDestroy(x);
+    if (h->p2_done) (void)hipEventDestroy(h->p2_done);
+    for (hipEvent_t e : h->rest_done)
+        if (e) (void)hipEventDestroy(e);
+    if (h->word) (void)hipFree(h->word);
+    if (h->copies_buf) (void)hipFree(h->copies_buf);
+    delete h;
+}
+
+// Whether a full solve of an n-vertex matrix uses the one-round lookahead,
+// and whether it runs round pairs (at the current thresholds).
+bool uses_lookahead(int64_t n) {
+    const int b = round_width(n);
+    const int64_t q = (n + b - 1) / b;
+    return q >= (b != kRoundB ? kW64LookaheadRounds : 3);
+}
+
+bool uses_pairs(int64_t n) {
+    const int b = round_width(n);
+    const int64_t q = (n + b - 1) / b;
+    return b == kRoundB && uses_lookahead(n) && q >= g_pair_rounds.load() && q >= 2;
+}
+
 // Timing events of one profiled solve.
 struct Timer {
     std::vector<hipEvent_t> ev;
@@ -201,6 +228,50 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+int64_t stream_state_bytes(int64_t n, int dtype) {
+    if (n <= 0 || !(uses_lookahead(n) || dtype == 0)) return 0;
+    return 256 + (uses_pairs(n) ? (int64_t)pair_copies_bytes(n) : 0);
+}
+
+int64_t stream_state_count() {
+    std::lock_guard<std::mutex> lock(g_map_mu);
+    return (int64_t)g_helpers.size();
+}
+
+hipError_t release_stream_state(hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        note_error("hipGetDevice", e);
+        return e;
+    }
+    const auto key = std::make_pair(dev, s);
+    Helper *h = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_map_mu);
+        auto it = g_helpers.find(key);
+        if (it == g_helpers.end()) return hipSuccess;
+        h = it->second;
+    }
+    {
+        // no solve is enqueuing on these streams while we wait for them
+        std::lock_guard<std::mutex> lock(h->mu);
+        // kernels on `s` read the word and the copies; the helper streams'
+        // kernels too
+        e = hipStreamSynchronize(s);
+        for (hipStream_t x : h->side)
+            if (e == hipSuccess) e = hipStreamSynchronize(x);
+        if (e != hipSuccess) {
+            note_error("hipStreamSynchronize (releasing a stream's state)", e);
+            return e;
+        }
+        std::lock_guard<std::mutex> lock2(g_map_mu);
+        g_helpers.erase(key);
+    }
+    destroy_helper(h);
+    return hipSuccess;
+}
+
 hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0, int64_t r1,
                       bool prologue, hipStream_t s, PhaseTimes *times) {
     // Round width: 64 for small matrices (apsp_small.hip), else 128.
@@ -215,7 +286,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     // Lookahead needs a round r+1 with a non-empty rest set; for a few
     // rounds of 64 the rest set is a handful of tiles and the cross-stream
     // events cost more than the overlap gains.
-    const bool lookahead = q >= (w64 ? kW64LookaheadRounds : 3);
+    const bool lookahead = uses_lookahead(n);
     const int bands = q >= kMinBandRounds ? kBands : 1;
     hipError_t herr = hipSuccess;
     Helper *h = (lookahead || dtype == 0) ? helper_for(s, &herr) : nullptr;

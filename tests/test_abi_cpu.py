@@ -182,7 +182,7 @@ def test_status_strings_and_widths(lib):
 
 
 def test_width64_limit_setter(lib):
-    """No HIP call: the width-64 limit is process-wide, in [0, 4096]."""
+    """No HIP call: the width-64 limit is process-wide, in [0, 8192]."""
     prev = lib.apsp_set_width64_max_n(300)
     try:
         assert prev >= 0
@@ -204,6 +204,28 @@ def test_round_pair_threshold_setter(lib):
         assert lib.apsp_set_round_pair_threshold(10) == 9
     finally:
         lib.apsp_set_round_pair_threshold(prev)
+
+
+def test_stream_state_bytes(lib):
+    """No HIP call: the per-stream state a full solve creates.  fp32 solves
+    below the lookahead (16 rounds of 64) keep none; int32 solves keep the
+    256-byte scan word; from 72 rounds of 128 the pair copies, 8 x 128 x 128q
+    words, come on top."""
+    f32, i32 = 1, 0
+    assert lib.apsp_stream_state_bytes(0, f32) == 0
+    assert lib.apsp_stream_state_bytes(1000, f32) == 0
+    assert lib.apsp_stream_state_bytes(1000, i32) == 256
+    assert lib.apsp_stream_state_bytes(8192, f32) == 256       # 64 rounds: lookahead only
+    assert lib.apsp_stream_state_bytes(16384, f32) == 256 + 8 * 128 * 16384 * 4
+    assert lib.apsp_stream_state_bytes(16385, i32) == 256 + 8 * 128 * 16512 * 4
+    assert lib.apsp_stream_state_bytes(100, 7) == -1
+    assert lib.apsp_stream_state_bytes(-1, f32) == -1
+    prev = lib.apsp_set_round_pair_threshold(1 << 20)  # no pairs at any size
+    try:
+        assert lib.apsp_stream_state_bytes(16384, f32) == 256
+    finally:
+        lib.apsp_set_round_pair_threshold(prev)
+    assert lib.apsp_stream_state_count() >= 0
 
 
 def test_binding_rejects_host_tensors():

@@ -124,3 +124,81 @@ def test_admission_under_small_budget(apsp):
     assert stats["done"] == len(sizes) - 1
     for r in reqs[:-1]:
         assert torch.equal(r.result, _alone(apsp, r, dev))
+
+
+@pytest.mark.parametrize("policy", ["srpt", "fifo"])
+def test_forced_failures_resume_from_checkpoints(apsp, policy):
+    """Slices forced to fail from the host (the backend reports the slice
+    failed and overwrites the matrix): each such request resumes from its last
+    good checkpoint and still ends with the bits of the solve alone."""
+    import torch
+
+    from paper_1902_04446_amd.serving import ApspServer, GpuBackend
+
+    dev = torch.device("cuda:0")
+    sizes = [1024, 2048, 300, 1100, 256]
+    reqs = _requests(sizes, 950)
+    # rounds of 64: 16, 32, 5, 18, 4; the failing slices hold these rounds
+    fail_at = {0: 9, 1: 21, 3: 4}
+    backend = GpuBackend(dev, slots=3, keep_results=True, fail_at=fail_at)
+    srv = ApspServer(backend, hbm_budget=1 << 30, slots=3, slice_rounds=3, inflight=2,
+                     checkpoint_rounds=6, policy=policy, max_running=2)
+    stats = srv.run(reqs, realtime=False)
+    torch.cuda.synchronize()
+    assert stats["done"] == len(sizes) and srv.used == 0
+    assert not backend.fail_at  # every forced failure happened
+    for r in reqs:
+        assert r.retries == (1 if r.rid in fail_at else 0), r.rid
+        assert torch.equal(r.result, _alone(apsp, r, dev)), r.n
+
+
+def test_stream_state_released_with_the_stream(apsp):
+    """A server that creates and drops streams does not accumulate solver
+    state: releasing a stream's state frees it (and a later solve on the
+    stream recreates it), and the state of a round-pair solve is the size
+    apsp_stream_state_bytes reports."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    base = apsp.stream_state_count()
+    n = 300
+    u, v, w = gg.swiss_roll_knn(n, gg.CFG_TEST, 990)
+    W = gg.dense_from_edges(n, u, v, w, np.int32)
+    ref = oracle.fw(W)
+    for i in range(5):
+        s = torch.cuda.Stream(dev)
+        D = torch.from_numpy(W).to(dev)
+        apsp.solve(D, stream=s)          # int32: keeps the scan word per stream
+        assert apsp.stream_state_count() == base + 1
+        apsp.release_stream_state(s)
+        assert apsp.stream_state_count() == base
+        assert np.array_equal(D.cpu().numpy().astype(np.int64), ref)
+    apsp.release_stream_state(torch.cuda.Stream(dev))  # no state: a no-op
+    assert apsp.stream_state_count() == base
+    # round pairs at width 128 from 3 rounds: the copies come with the state
+    prev_w = apsp.set_width64_max_n(0)
+    prev_p = apsp.set_round_pair_threshold(3)
+    try:
+        n = 2048
+        u, v, w = gg.swiss_roll_knn(n, gg.CFG_TEST, 991)
+        D = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+        want = apsp.stream_state_bytes(n, apsp.APSP_F32)
+        assert want == 256 + 8 * 128 * 2048 * 4
+        s = torch.cuda.Stream(dev)
+        torch.cuda.synchronize()
+        apsp.solve(D, stream=s)
+        torch.cuda.synchronize()
+        free_before, _ = torch.cuda.mem_get_info(dev)
+        apsp.release_stream_state(s)
+        free_after, _ = torch.cuda.mem_get_info(dev)
+        assert free_after - free_before >= 8 * 128 * 2048 * 4
+        assert apsp.stream_state_count() == base
+        E = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+        apsp.solve(E, stream=s)          # recreated on demand, same bits
+        torch.cuda.synchronize()
+        assert torch.equal(D, E)
+        apsp.release_stream_state(s)
+    finally:
+        apsp.set_round_pair_threshold(prev_p)
+        apsp.set_width64_max_n(prev_w)
+    assert apsp.stream_state_count() == base

@@ -147,6 +147,104 @@ def test_failed_slice_is_retried_then_gives_up():
     assert reqs2[0].status == "failed" and srv2.used == 0
 
 
+@pytest.mark.parametrize("inflight", [1, 3])
+def test_retry_resumes_from_the_last_good_checkpoint(inflight):
+    """A slice of rounds 4..5 fails (forced): the request resumes from the
+    checkpoint at round 4, not from round 0, and ends with every round applied
+    once in order; with inflight 3 the slices enqueued behind the failed one
+    ran on bad data and are discarded with it."""
+    clock = Clock()
+    be = SimBackend(rate=1e12, b=64, clock=clock, fail_at={0: 5})
+    srv = ApspServer(be, hbm_budget=1 << 36, slots=1, slice_rounds=2, inflight=inflight,
+                     checkpoint_rounds=4, clock=clock)
+    reqs = mk([1024])          # 16 rounds of 64
+    drive(srv, clock, reqs)
+    r = reqs[0]
+    assert r.status == "done" and r.retries == 1
+    assert r.result == list(range(16))
+    assert be.loads == 1 and be.restores == 1
+    assert srv.used == 0
+
+
+def test_retry_without_checkpoints_reingests_the_input():
+    clock = Clock()
+    be = SimBackend(rate=1e12, b=64, clock=clock, fail_at={0: 9})
+    srv = ApspServer(be, hbm_budget=1 << 36, slots=1, slice_rounds=2, clock=clock)
+    reqs = mk([1024])
+    drive(srv, clock, reqs)
+    assert reqs[0].status == "done" and reqs[0].result == list(range(16))
+    assert be.loads == 2 and be.restores == 0
+
+
+def test_checkpoints_count_against_the_budget():
+    clock = Clock()
+    be = SimBackend(clock=clock)
+    srv = ApspServer(be, hbm_budget=2 * be.bytes_needed(1000), slots=2, checkpoint_rounds=4,
+                     clock=clock)
+    reqs = mk([1000])
+    drive(srv, clock, reqs)
+    assert reqs[0].status == "rejected"      # matrix + 2 checkpoint buffers > 2 matrices
+
+
+def test_srpt_serves_the_least_remaining_work_first():
+    # one request runs at a time: a small request arriving behind a large one
+    # gets the device at the large one's next slice boundary under srpt, and
+    # waits for it to finish under fifo
+    out = {}
+    for policy in ("srpt", "fifo"):
+        clock = Clock()
+        be = SimBackend(rate=1e12, clock=clock)
+        srv = ApspServer(be, hbm_budget=1 << 36, slots=2, slice_rounds=1, inflight=1,
+                         policy=policy, max_running=1, clock=clock)
+        reqs = mk([4096, 256], arrivals=[0.0, 0.001])
+        drive(srv, clock, reqs, dt=1e-5, limit=1e7)
+        big, small = reqs
+        assert big.status == small.status == "done"
+        out[policy] = (small.done < big.done)
+    assert out == {"srpt": True, "fifo": False}
+
+
+def test_large_requests_run_one_at_a_time():
+    clock = Clock()
+    be = SimBackend(rate=1e12, clock=clock)
+    srv = ApspServer(be, hbm_budget=1 << 40, slots=4, slice_rounds=2, policy="fifo",
+                     large_n=4096, max_large=1, clock=clock)
+    reqs = mk([4096, 8192, 256, 4096, 512], arrivals=[0.0, 0.0, 0.001, 0.002, 0.003])
+    peak = 0
+    i = 0
+    while i < len(reqs) or not srv.idle():
+        while i < len(reqs) and reqs[i].arrival <= clock.t:
+            srv.submit(reqs[i])
+            i += 1
+        srv.step(clock.t)
+        peak = max(peak, sum(1 for r in srv.active if r.n >= 4096 and r.inflight))
+        clock.t += 1e-4
+    assert peak == 1
+    assert all(r.status == "done" for r in reqs)
+    # the small ones ran beside the large ones and finished first
+    assert reqs[2].done < reqs[0].done and reqs[4].done < reqs[1].done
+    # fifo among the large ones
+    assert reqs[0].done < reqs[1].done < reqs[3].done
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        ApspServer(SimBackend(), hbm_budget=1, policy="lifo")
+
+
+def test_warmup_requests_are_left_out_of_latency():
+    from paper_1902_04446_amd.serving import summarize
+
+    reqs = mk([256, 256, 512], arrivals=[0.0, 1.0, 2.0])
+    for r, lat in zip(reqs, (5.0, 0.001, 0.002)):
+        r.status, r.done = "done", r.arrival + lat
+    st = summarize(reqs, 3.0, warmup=1)
+    assert st["warmup_excluded"] == 1 and st["done"] == 3
+    assert st["p99_ms"] == pytest.approx(2.0)
+    assert st["per_size"]["256"]["count"] == 1
+    assert st["per_size"]["512"]["p50_ms"] == pytest.approx(2.0)
+
+
 def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert percentile(v, 50) == 50
