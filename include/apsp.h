@@ -117,17 +117,20 @@ int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *strea
 int32_t apsp_set_round_pair_threshold(int32_t rounds);
 
 /*
- * Per-stream state.  apsp_solve, apsp_solve_rounds and apsp_solve_profiled
- * keep, per (device, caller stream), the state apsp_solve describes: two
- * helper streams, three events, the 256-byte scan word and, once a solve ran
- * round pairs, the panel copies.  int32 solves and solves long enough for the
+ * Per-stream state.  apsp_solve, apsp_solve_rounds, apsp_solve_profiled and
+ * apsp_solve_symmetric keep, per (device, caller stream), the state
+ * apsp_solve describes: two helper streams, three events, the 256-byte scan
+ * word and, once a solve ran round pairs or a symmetric solve of 2 or more
+ * rounds ran, the panel copies.  int32 solves and solves long enough for the
  * lookahead create it; it lives until released here or the process ends.
  *
- * apsp_stream_state_bytes -- device bytes of that state after a full solve
- * of an n-vertex `dtype` matrix on a stream without state: 0 when such a
- * solve creates none, else 256 plus the copies when it runs round pairs (at
- * the current thresholds).  A stream's copies grow to its largest solve and
- * never shrink.  No HIP call.  Returns -1 for a bad dtype or n out of range.
+ * apsp_stream_state_bytes -- device bytes of that state after a full
+ * apsp_solve of an n-vertex `dtype` matrix on a stream without state: 0 when
+ * such a solve creates none, else 256 plus the copies when it runs round
+ * pairs (at the current thresholds).  (apsp_solve_symmetric of n > 128 keeps
+ * 256 plus the copies for n.)  A stream's copies grow to its largest solve
+ * and never shrink.  No HIP call.  Returns -1 for a bad dtype or n out of
+ * range.
  *
  * apsp_stream_state_count -- how many (device, stream) states the process
  * holds.  No HIP call.
@@ -191,8 +194,16 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
  * of the input is read (the lower is overwritten).  Rounds are 128 wide.
  * For a symmetric input the result equals the 128-wide blocked method's bit
  * for bit (fp32 addition commutes; apsp_solve's whenever apsp_round_width(n)
- * is 128), with about half of its phase-2/3 work.  Single stream, no lookahead;
- * asynchronous; allocates nothing.  Returns as apsp_solve.
+ * is 128), with about half of its phase-2/3 work.  Phase 2 also writes block
+ * row r whole into a copy (the row blocks as they are, the column blocks
+ * transposed: by symmetry both are row r), from which phase 3 reads both of
+ * its operands.  From 3 rounds on, the bulk of each round's phase 3 runs on
+ * a helper stream of `stream` while phases 1 and 2 of the next round run on
+ * `stream`, as in apsp_solve.  From 2 rounds on the call uses the per-stream
+ * state of apsp_solve (helper streams, and the panel copies, of which it
+ * uses two slots: 256 + 8 x 128 x 128q x 4 bytes, allocated or grown as
+ * described there).  Asynchronous.  Returns as apsp_solve, or
+ * APSP_ERR_NO_MEMORY when the copies cannot be allocated.
  */
 int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
 

@@ -186,11 +186,8 @@ int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, v
     if ((n + apsp::kRoundB - 1) / apsp::kRoundB > 46000) return APSP_ERR_INVALID_VALUE;
     const hipError_t e = apsp::run_symmetric(static_cast<uint32_t *>(dist), n, ld, dtype,
                                              reinterpret_cast<hipStream_t>(stream));
-    if (e != hipSuccess) {
-        apsp::note_error("symmetric solve launch", e);
-        return APSP_ERR_DEVICE;
-    }
-    return APSP_OK;
+    if (e == hipErrorOutOfMemory) return APSP_ERR_NO_MEMORY;
+    return e == hipSuccess ? APSP_OK : APSP_ERR_DEVICE;
 }
 
 int32_t apsp_validate(const void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {

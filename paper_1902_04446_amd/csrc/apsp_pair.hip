@@ -216,40 +216,13 @@ __device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
 
 // The rest pass of a pair with direct staging (full tiles of an aligned fp32
 // matrix): the column panels from their transposed copies, the row panels
-// from the matrix.  The output tile is addressed as one uniform base pointer
-// plus 32-bit lane offsets (the caller guarantees 128 ld < 2^30), and the
-// offsets are formed again for the store (the empty asm statements hide that
-// base and ld are unchanged), so no 64-bit row address stays live across the
-// products: that keeps the kernel at 128 registers without spilling.
-__device__ __forceinline__ void tile_io_direct(uint32_t (&acc)[8][8], uint32_t *base, uint32_t ld,
-                                               bool store) {
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const uint32_t off = (uint32_t)tile::row_of(m, ty) * ld + (uint32_t)tx * 4u;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            uint32_t *p = base + off + h * 64;
-            if (store) {
-                tile::st4_stream(p, make_uint4(acc[m][h * 4 + 0], acc[m][h * 4 + 1],
-                                               acc[m][h * 4 + 2], acc[m][h * 4 + 3]));
-            } else {
-                const uint4 v = tile::ld4_stream(p);
-                acc[m][h * 4 + 0] = v.x;
-                acc[m][h * 4 + 1] = v.y;
-                acc[m][h * 4 + 2] = v.z;
-                acc[m][h * 4 + 3] = v.w;
-            }
-        }
-    }
-}
-
+// from the matrix; the output tile through tile::io_direct.
 template <int MODE>
 __device__ __forceinline__ void pair_direct_update(const PairArgs &a, tile::Lds &L) {
     const Job jb = job_of<MODE>(a);
     const int64_t i0 = (int64_t)jb.I * TB, j0 = (int64_t)jb.J * TB;
     uint32_t acc[8][8];
-    tile_io_direct(acc, a.D + i0 * a.ld + j0, (uint32_t)a.ld, false);
+    tile::io_direct(acc, a.D + i0 * a.ld + j0, (uint32_t)a.ld, false);
     // product 0: round prev+1's deferred update from the copies (pending
     // tiles only); product 1: rounds r and r+1.  One call site keeps the
     // register count at 4 workgroups per CU.
@@ -265,7 +238,7 @@ __device__ __forceinline__ void pair_direct_update(const PairArgs &a, tile::Lds 
     uint32_t *base = a.D + i0 * a.ld + j0;
     uint32_t ld = (uint32_t)a.ld;
     asm volatile("" : "+s"(base), "+s"(ld));
-    tile_io_direct(acc, base, ld, true);
+    tile::io_direct(acc, base, ld, true);
 }
 
 template <class Op, int MODE>

@@ -238,6 +238,26 @@ int64_t stream_state_count() {
     return (int64_t)g_helpers.size();
 }
 
+hipError_t side_resources(hipStream_t s, int64_t n, SideResources *out,
+                          std::unique_lock<std::mutex> *lock) {
+    hipError_t err = hipSuccess;
+    Helper *h = helper_for(s, &err);
+    if (!h) return err;
+    std::unique_lock<std::mutex> lk(h->mu);
+    if (!ensure_copies(h, n, s)) {
+        note_message("the symmetric solve's row-panel copies could not be allocated");
+        return hipErrorOutOfMemory;
+    }
+    out->side = h->side[0];
+    out->p2_done = h->p2_done;
+    out->rest_done = h->rest_done[0];
+    out->slot[0] = h->copies.row[0];
+    out->slot[1] = h->copies.row[1];
+    out->ld = h->copies.ld;
+    *lock = std::move(lk);
+    return hipSuccess;
+}
+
 hipError_t release_stream_state(hipStream_t s) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);

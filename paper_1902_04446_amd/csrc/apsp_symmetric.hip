@@ -5,15 +5,28 @@
 //
 //   phase 2  row panel (r, J), J > r: D_rJ = min(D_rJ, D_rr (x) D_rJ);
 //            column panel (I, r), I < r: D_Ir = min(D_Ir, D_Ir (x) D_rr);
-//   phase 3  (I, J), I <= J, I, J != r: D_IJ = min(D_IJ, D_Ir (x) D_rJ), where
-//            D_Ir for I > r is read as the transpose of (r, I) and D_rJ for
-//            J < r as the transpose of (J, r) (tile::minplus_tile_ab, TA/TB);
+//   phase 3  (I, J), I <= J, I, J != r: D_IJ = min(D_IJ, D_Ir (x) D_rJ).
 //
-// and the strict lower triangle is filled from the upper one at the end (and
+// Phase 3 needs D_Ir for I > r and D_rJ for J < r, blocks below the
+// diagonal.  By symmetry both are pieces of block row r: D_Ir[i][k] =
+// D_rI[k][i] and D_rJ = D_Jr^T.  So phase 2 writes each panel block it
+// produces a second time, into a copy R of block row r (128 x 128q words):
+// R[k][x] = D_rx, taken from the row block (r, x) as is for x > r and from
+// the column block (x, r) transposed for x < r.  Phase 3 then reads only R:
+// D_IJ = min(D_IJ, R_I^T (x) R_J), R_I the 128 columns of block I of R, both
+// operands k-major, which is the layout direct-to-LDS staging needs.
+//
+// Every candidate D_Ik + D_kJ of the full method is formed here from the
+// same two values (fp32 addition is commutative), so the result is the
+// full method's, bit for bit, at about half its phase-2 and phase-3 work.
+// The strict lower triangle is filled from the upper one at the end (and
 // once before the first round, so the input's lower triangle is never read).
-// Every candidate D_Ik + D_kJ of block (J, I) in the full method equals
-// D_kJ + D_Ik here (fp32 addition is commutative), so the result is the full
-// method's, bit for bit, at about half its phase-2 and phase-3 work.
+//
+// Rounds overlap as in the full solver: phase 3 of round r is split into the
+// tiles in block row/column r+1 (with the closure of diagonal block r+1,
+// phase 1 of round r+1, fused), which stay on the caller's stream, and the
+// rest, which a helper stream runs while the caller's stream goes on with
+// phase 2 of round r+1.  The copies of rounds r and r+1 use two slots.
 #include "apsp_tile.h"
 
 namespace apsp {
@@ -23,60 +36,28 @@ namespace {
 using tile::NT;
 using tile::TB;
 
-template <class Op>
-__device__ __forceinline__ void sym_product(uint32_t (&acc)[8][8], uint32_t *D, int64_t ld, int I,
-                                            int J, int r, int64_t i0, int64_t j0, int64_t kb,
-                                            int mr, int nc, int kw, bool vec, tile::Lds &L) {
-    const bool ta = I > r, tb = J < r;
-    // direct A = D[i0.., kb..]; transposed A from block (r, I) = D[kb.., i0..]
-    // direct B = D[kb.., j0..]; transposed B from block (J, r) = D[j0.., kb..]
-    if (!ta && !tb)
-        tile::minplus_tile_ab<Op, false, false, false>(acc, D + kb, ld, D + kb * ld, ld, i0, j0,
-                                                       mr, nc, kw, vec, L);
-    else if (ta && !tb)
-        tile::minplus_tile_ab<Op, false, true, false>(acc, D + kb * ld, ld, D + kb * ld, ld, i0, j0,
-                                                      mr, nc, kw, vec, L);
-    else if (!ta && tb)
-        tile::minplus_tile_ab<Op, false, false, true>(acc, D + kb, ld, D + kb, ld, i0, j0, mr, nc,
-                                                      kw, vec, L);
-    else
-        tile::minplus_tile_ab<Op, false, true, true>(acc, D + kb * ld, ld, D + kb, ld, i0, j0, mr,
-                                                     nc, kw, vec, L);
-}
+enum SymSet {
+    kSymAll = 0,   // every upper tile outside block row/column r, (q-1) q / 2
+    kSymRest = 1,  // outside block rows/columns r and r+1, (q-2) (q-1) / 2
+    kSymNext = 2,  // the upper tiles in block row/column r+1, diagonal first, q-1
+};
 
-// MODE 0: the q-1 upper panel blocks of round r; MODE 1: the upper blocks
-// outside block row/column r, with the closure of diagonal block r+1 fused.
-template <class Op, int MODE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_sym(
-    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag) {
+// Phase 2 of round r: tiles (r, J), J > r, then (I, r), I < r (q-1 of them),
+// stored in place and into R (row block as is, column block transposed).
+template <class Op>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_panels(
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec,
+    uint32_t *__restrict__ R, int64_t ldr) {
     __shared__ tile::Lds L;
+    tile::chain_priority();
+    const int t = blockIdx.x;
     int I, J;
-    if (MODE == 0) {
-        const int t = blockIdx.x;
-        if (t < q - 1 - r) {
-            I = r;
-            J = r + 1 + t;
-        } else {
-            I = t - (q - 1 - r);
-            J = r;
-        }
+    if (t < q - 1 - r) {
+        I = r;
+        J = r + 1 + t;
     } else {
-        // upper triangle (a <= b) of the (q-1) x (q-1) grid without block r,
-        // row-major; each XCD (wg % 8) gets one contiguous range of it
-        const int m = q - 1;
-        const int T = m * (m + 1) / 2;
-        const int wg = blockIdx.x;
-        const int x = wg & 7, s = wg >> 3;
-        const int per = T >> 3, rem = T & 7;
-        int id = x * per + (x < rem ? x : rem) + s;
-        int a = 0;
-        while (id >= m - a) {  // row a holds m - a entries
-            id -= m - a;
-            ++a;
-        }
-        const int b = a + id;
-        I = a < r ? a : a + 1;
-        J = b < r ? b : b + 1;
+        I = t - (q - 1 - r);
+        J = r;
     }
     const int64_t i0 = (int64_t)I * TB, j0 = (int64_t)J * TB, kb = (int64_t)r * TB;
     const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
@@ -84,10 +65,101 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int nc = (int)((n - j0) < TB ? (n - j0) : TB);
     uint32_t acc[8][8];
     tile::load_acc<Op, false>(acc, D, ld, i0, j0, mr, nc, vec);
-    sym_product<Op>(acc, D, ld, I, J, r, i0, j0, kb, mr, nc, kw, vec, L);
-    if (MODE == 1 && close_diag && I == r + 1 && J == r + 1)
-        tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+    tile::minplus_tile<Op, false>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
     tile::store_acc<Op>(acc, D, ld, i0, j0, mr, nc, vec);
+    if (I == r)
+        tile::store_acc<Op>(acc, R, ldr, 0, j0, mr, nc, true);  // rows are k (mr == kw)
+    else
+        tile::store_acc_t<Op>(acc, R, ldr, i0, mr, nc);  // columns are k (nc == kw)
+}
+
+// Upper-triangle tile of a phase-3 set: the a <= b entries of the m x m grid
+// of block indices without the `skip` indices r .. r+skip-1, row-major, each
+// XCD (workgroup w runs on XCD w % 8) dealt one contiguous range of them.
+__device__ __forceinline__ void upper_tile(int wg, int r, int q, int skip, int &I, int &J) {
+    const int m = q - skip;
+    const int T = m * (m + 1) / 2;
+    const int x = wg & 7, s = wg >> 3;
+    const int per = T >> 3, rem = T & 7;
+    const int id = x * per + (x < rem ? x : rem) + s;
+    // rows before row a hold start(a) = a m - a (a - 1) / 2 entries
+    auto start = [&](int a) { return a * m - a * (a - 1) / 2; };
+    const double w = 2.0 * m + 1.0;
+    int a = (int)((w - sqrt(w * w - 8.0 * id)) * 0.5);
+    a = a < 0 ? 0 : (a > m - 1 ? m - 1 : a);
+    while (a + 1 < m && start(a + 1) <= id) ++a;
+    while (a > 0 && start(a) > id) --a;
+    const int b = a + (id - start(a));
+    I = a < r ? a : a + skip;
+    J = b < r ? b : b + skip;
+}
+
+template <int SET>
+__device__ __forceinline__ void sym_tile_of(int wg, int r, int q, int &I, int &J) {
+    if (SET == kSymNext) {
+        if (wg < q - 1 - r) {  // (r+1, r+1) first: its closure is the chain
+            I = r + 1;
+            J = r + 1 + wg;
+        } else {
+            I = wg - (q - 1 - r);
+            J = r + 1;
+        }
+    } else {
+        upper_tile(wg, r, q, SET == kSymRest ? 2 : 1, I, J);
+    }
+}
+
+// Phase 3 on a tile set from R.  DIRECT: n a multiple of 128 and D's rows
+// 16-byte aligned, every tile full; both operands staged straight into LDS.
+// Otherwise the register-staged loader reads A transposed from R with the
+// tile's bounds.  kSymNext (and kSymAll with `close`) closes diagonal block
+// r+1 after its update.
+template <class Op, int SET, bool DIRECT>
+__device__ __forceinline__ void sym_update(uint32_t *D, int64_t ld, int64_t n, int r, int q,
+                                           int vec, const uint32_t *R, int64_t ldr, int close,
+                                           tile::Lds &L) {
+    int I, J;
+    sym_tile_of<SET>(blockIdx.x, r, q, I, J);
+    const int64_t i0 = (int64_t)I * TB, j0 = (int64_t)J * TB, kb = (int64_t)r * TB;
+    const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
+    const int mr = (int)((n - i0) < TB ? (n - i0) : TB);
+    const int nc = (int)((n - j0) < TB ? (n - j0) : TB);
+    const bool closes = (SET == kSymNext || close) && I == r + 1 && J == r + 1;
+    uint32_t acc[8][8];
+    if (DIRECT) {
+        tile::io_direct(acc, D + i0 * ld + j0, (uint32_t)ld, false);
+        tile::minplus_tile_direct<Op>(acc, R, R, TB, ldr, R, ldr, i0, j0, TB, L);
+        if (closes) tile::close_block<Op>(acc, TB, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+        uint32_t *base = D + i0 * ld + j0;
+        uint32_t ldu = (uint32_t)ld;
+        asm volatile("" : "+s"(base), "+s"(ldu));
+        tile::io_direct(acc, base, ldu, true);
+    } else {
+        tile::load_acc<Op, false>(acc, D, ld, i0, j0, mr, nc, vec);
+        tile::minplus_tile_ab<Op, false, true, false>(acc, R, ldr, R, ldr, i0, j0, mr, nc, kw,
+                                                      true, L);
+        if (closes) tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+        tile::store_acc<Op>(acc, D, ld, i0, j0, mr, nc, vec);
+    }
+}
+
+// The bulk set on the helper stream: 4 workgroups per CU in direct form.
+template <class Op, bool DIRECT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DIRECT ? 4 : 3))) void k_sym_rest(
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec,
+    const uint32_t *__restrict__ R, int64_t ldr) {
+    __shared__ tile::Lds L;
+    sym_update<Op, kSymRest, DIRECT>(D, ld, n, r, q, vec, R, ldr, 0, L);
+}
+
+// The caller-stream sets (kSymNext, kSymAll): they carry the closure.
+template <class Op, int SET, bool DIRECT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sym_chain(
+    uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec,
+    const uint32_t *__restrict__ R, int64_t ldr, int close) {
+    __shared__ tile::Lds L;
+    tile::chain_priority();
+    sym_update<Op, SET, DIRECT>(D, ld, n, r, q, vec, R, ldr, close, L);
 }
 
 // Fill the strict lower triangle from the upper one, in 64 x 64 blocks:
@@ -116,14 +188,55 @@ __global__ __launch_bounds__(256) void k_mirror(uint32_t *__restrict__ D, int64_
     }
 }
 
-template <class Op>
-void launch_sym(int mode, uint32_t *D, int64_t ld, int64_t n, int r, int q, int vec, int close,
-                hipStream_t s, unsigned grid) {
-    if (mode == 0)
-        hipLaunchKernelGGL((k_sym<Op, 0>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
-    else
-        hipLaunchKernelGGL((k_sym<Op, 1>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close);
+unsigned set_size(int set, int q) {
+    switch (set) {
+    case kSymAll: return (unsigned)((q - 1) * q / 2);
+    case kSymRest: return (unsigned)((q - 2) * (q - 1) / 2);
+    default: return (unsigned)(q - 1);
+    }
 }
+
+struct SymLaunch {
+    uint32_t *D;
+    int64_t ld, n;
+    int q, vec, dtype;
+    bool direct;
+
+    template <class Op>
+    hipError_t panels_t(int r, uint32_t *R, int64_t ldr, hipStream_t s) const {
+        hipLaunchKernelGGL((k_sym_panels<Op>), dim3((unsigned)(q - 1)), dim3(NT), 0, s, D, ld, n,
+                           r, q, vec, R, ldr);
+        return hipGetLastError();
+    }
+    hipError_t panels(int r, uint32_t *R, int64_t ldr, hipStream_t s) const {
+        return dtype == 0 ? panels_t<OpI32>(r, R, ldr, s) : panels_t<OpF32>(r, R, ldr, s);
+    }
+
+    template <class Op, bool DIRECT>
+    hipError_t update_t(int r, int set, const uint32_t *R, int64_t ldr, int close,
+                        hipStream_t s) const {
+        const unsigned g = set_size(set, q);
+        if (g == 0) return hipSuccess;
+        if (set == kSymRest)
+            hipLaunchKernelGGL((k_sym_rest<Op, DIRECT>), dim3(g), dim3(NT), 0, s, D, ld, n, r, q,
+                               vec, R, ldr);
+        else if (set == kSymNext)
+            hipLaunchKernelGGL((k_sym_chain<Op, kSymNext, DIRECT>), dim3(g), dim3(NT), 0, s, D,
+                               ld, n, r, q, vec, R, ldr, close);
+        else
+            hipLaunchKernelGGL((k_sym_chain<Op, kSymAll, DIRECT>), dim3(g), dim3(NT), 0, s, D,
+                               ld, n, r, q, vec, R, ldr, close);
+        return hipGetLastError();
+    }
+    hipError_t update(int r, int set, const uint32_t *R, int64_t ldr, int close,
+                      hipStream_t s) const {
+        if (dtype == 0)
+            return direct ? update_t<OpI32, true>(r, set, R, ldr, close, s)
+                          : update_t<OpI32, false>(r, set, R, ldr, close, s);
+        return direct ? update_t<OpF32, true>(r, set, R, ldr, close, s)
+                      : update_t<OpF32, false>(r, set, R, ldr, close, s);
+    }
+};
 
 }  // namespace
 
@@ -131,37 +244,62 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
     if (n <= 0) return hipSuccess;
     const int nb = (int)((n + 63) / 64);
     const dim3 mgrid((unsigned)((int64_t)nb * (nb + 1) / 2));
+    auto mirror = [&]() {
+        hipLaunchKernelGGL(k_mirror, mgrid, dim3(256), 0, s, D, ld, n, nb);
+        return hipGetLastError();
+    };
     hipError_t e = launch_prologue(D, n, ld, dtype, s);
     // the input's lower triangle is not read: make the matrix symmetric first
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_mirror, mgrid, dim3(256), 0, s, D, ld, n, nb);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = mirror();
+    if (e == hipSuccess) e = launch_phase1(D, n, ld, dtype, 0, s);
     const int q = (int)((n + TB - 1) / TB);
-    const int vec = ((reinterpret_cast<uintptr_t>(D) & 15u) == 0 && (ld & 3) == 0) ? 1 : 0;
-    bool closed = false;
-    for (int r = 0; r < q && e == hipSuccess; ++r) {
-        if (!closed) e = launch_phase1(D, n, ld, dtype, r, s);
-        closed = false;
-        if (q > 1 && e == hipSuccess) {
-            const unsigned g2 = (unsigned)(q - 1);
-            const unsigned g3 = (unsigned)((q - 1) * q / 2);
-            const int fuse = r + 1 < q ? 1 : 0;
-            if (dtype == 0) {
-                launch_sym<OpI32>(0, D, ld, n, r, q, vec, 0, s, g2);
-                launch_sym<OpI32>(1, D, ld, n, r, q, vec, fuse, s, g3);
+    if (q == 1 || e != hipSuccess) return e == hipSuccess ? mirror() : e;
+
+    SideResources res;
+    std::unique_lock<std::mutex> lock;
+    e = side_resources(s, n, &res, &lock);
+    if (e != hipSuccess) return e;
+    SymLaunch L;
+    L.D = D;
+    L.ld = ld;
+    L.n = n;
+    L.q = q;
+    L.vec = ((reinterpret_cast<uintptr_t>(D) & 15u) == 0 && (ld & 3) == 0) ? 1 : 0;
+    L.dtype = dtype;
+    // full tiles, aligned rows, 32-bit lane offsets (128 ld and 128 ldr < 2^30)
+    L.direct = n % TB == 0 && L.vec && ld < ((int64_t)1 << 22) && res.ld < ((int64_t)1 << 22);
+
+    if (q == 2) {  // no rest set to overlap: round by round on the caller's stream
+        for (int r = 0; r < q && e == hipSuccess; ++r) {
+            uint32_t *R = res.slot[r & 1];
+            e = L.panels(r, R, res.ld, s);
+            if (e == hipSuccess) e = L.update(r, kSymAll, R, res.ld, r + 1 < q ? 1 : 0, s);
+        }
+    } else {
+        // round r: phase 2 (phase 1 ran fused in the previous round's next
+        // set), then the rest set on the helper stream once phase 2 is done,
+        // and the next set on the caller's stream after the previous round's
+        // rest set (it rewrites tiles in block row/column r+1, which that set
+        // wrote); the previous rest set also read the copy slot that phase 2
+        // of round r+1 overwrites, which that same wait orders.
+        for (int r = 0; r < q && e == hipSuccess; ++r) {
+            uint32_t *R = res.slot[r & 1];
+            e = L.panels(r, R, res.ld, s);
+            if (e == hipSuccess && r > 0) e = hipStreamWaitEvent(s, res.rest_done, 0);
+            if (e != hipSuccess) break;
+            if (r + 1 < q) {
+                e = hipEventRecord(res.p2_done, s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(res.side, res.p2_done, 0);
+                if (e == hipSuccess) e = L.update(r, kSymRest, R, res.ld, 0, res.side);
+                if (e == hipSuccess) e = hipEventRecord(res.rest_done, res.side);
+                if (e == hipSuccess) e = L.update(r, kSymNext, R, res.ld, 1, s);
             } else {
-                launch_sym<OpF32>(0, D, ld, n, r, q, vec, 0, s, g2);
-                launch_sym<OpF32>(1, D, ld, n, r, q, vec, fuse, s, g3);
+                e = L.update(r, kSymAll, R, res.ld, 0, s);
             }
-            closed = fuse != 0;
-            e = hipGetLastError();
         }
     }
-    if (e == hipSuccess) {  // blocks below the diagonal were not updated
-        hipLaunchKernelGGL(k_mirror, mgrid, dim3(256), 0, s, D, ld, n, nb);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = mirror();  // blocks below the diagonal were not updated
+    if (e != hipSuccess) note_error("symmetric solve launch", e);
     return e;
 }
 

@@ -435,6 +435,37 @@ __device__ __forceinline__ void minplus_tile_direct(uint32_t (&acc)[8][8], const
     }
 }
 
+// Load (store == false) or store a full 128 x 128 tile at `base` (leading
+// dimension ld, 16-byte aligned rows), in the accumulator layout, with no
+// conversion (the Ops whose memory form is their compute form: OpF32,
+// OpI32).  The tile is addressed as one uniform base pointer plus 32-bit lane
+// offsets (the caller guarantees 128 ld < 2^30); a caller that forms base and
+// ld again for the store behind an empty asm statement keeps no 64-bit row
+// address live across the products, which saves the registers of a
+// workgroup at 4 per CU.
+__device__ __forceinline__ void io_direct(uint32_t (&acc)[8][8], uint32_t *base, uint32_t ld,
+                                          bool store) {
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const uint32_t off = (uint32_t)row_of(m, ty) * ld + (uint32_t)tx * 4u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t *p = base + off + h * 64;
+            if (store) {
+                st4_stream(p, make_uint4(acc[m][h * 4 + 0], acc[m][h * 4 + 1], acc[m][h * 4 + 2],
+                                         acc[m][h * 4 + 3]));
+            } else {
+                const uint4 v = ld4_stream(p);
+                acc[m][h * 4 + 0] = v.x;
+                acc[m][h * 4 + 1] = v.y;
+                acc[m][h * 4 + 2] = v.z;
+                acc[m][h * 4 + 3] = v.w;
+            }
+        }
+    }
+}
+
 // Store the mr x nc tile transposed: dst[col * ldd + i0 + row] = C[row][col]
 // (Op::out applied), the layout minplus_tile_direct takes its A operand in.
 // dst and ldd must keep 16-byte alignment at i0 (i0 a multiple of 4).

@@ -1009,6 +1009,48 @@ def test_symmetric_variant_vs_oracle(apsp, dev, n):
         assert torch.equal(buf[mask], before[mask])
 
 
+@pytest.mark.parametrize("n,pad", [(256, 0), (384, 0), (384, 4), (384, 1), (1024, 0), (1280, 0)])
+def test_symmetric_variant_direct_and_lookahead_vs_oracle(apsp, dev, n, pad):
+    """Sizes that are multiples of 128 take the direct-staged phase 3 (with
+    16-byte aligned rows: pad 0 or 4; pad 1 takes the register-staged one),
+    and from 3 rounds on the rest set runs on the helper stream one round
+    ahead.  int32 equals Floyd-Warshall, fp32 the oracle's blocked model at
+    width 128, bit for bit."""
+    import torch
+
+    Wi, _ = _er(n, min(1.0, 4.0 / n), 9800 + n)
+    Wf, _ = _swiss(n, 9900 + n)
+    for W in (Wi, Wf):
+        view, _ = _to_dev(W, dev, ld=n + pad)
+        apsp.solve_symmetric(view)
+        torch.cuda.synchronize()
+        got = view.cpu().numpy()
+        if W.dtype == np.int32:
+            assert np.array_equal(got.astype(np.int64), oracle.fw(W, threads=8)), n
+        else:
+            assert np.array_equal(got, oracle.blocked(W, 128)), n
+
+
+def test_symmetric_variant_equals_full_solve_large(apsp, dev):
+    """n = 4096 (32 rounds, direct staging, lookahead): the upper-triangle
+    solve gives the full solve's bits at width 128 (checked against the
+    oracle at the sizes above)."""
+    import torch
+
+    n = 4096
+    Wf, _ = _swiss(n, 9990)
+    a, _ = _to_dev(Wf, dev)
+    b, _ = _to_dev(Wf, dev)
+    prev = apsp.set_width64_max_n(0)
+    try:
+        apsp.solve(a)
+        apsp.solve_symmetric(b)
+        torch.cuda.synchronize()
+    finally:
+        apsp.set_width64_max_n(prev)
+    assert torch.equal(a, b)
+
+
 # ------------------------------------------------- fp32 input with a diagonal
 
 def _f32_with_diagonal(n, seed):
