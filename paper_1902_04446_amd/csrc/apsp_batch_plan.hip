@@ -69,99 +69,132 @@ int32_t plan_build(apsp_batch_plan &p, void *const *ptrs, const int32_t *ns, con
 
     // Balance graphs over the 8 XCDs by work (longest first, least loaded
     // XCD), so each XCD's item list of every launch is about as long.
+    // (graphs by n descending, equal n in batch order: a counting sort)
     std::vector<int> order(G);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return descs[a].n > descs[b].n; });
+    {
+        int nmax = 0;
+        for (int g = 0; g < G; ++g) nmax = std::max(nmax, (int)descs[g].n);
+        std::vector<int> at((size_t)nmax + 2, 0);
+        for (int g = 0; g < G; ++g) ++at[(size_t)(nmax - descs[g].n) + 1];
+        for (int k = 1; k <= nmax + 1; ++k) at[(size_t)k] += at[(size_t)k - 1];
+        for (int g = 0; g < G; ++g) order[(size_t)at[(size_t)(nmax - descs[g].n)]++] = g;
+    }
     std::vector<int> xcd(G, 0);
-    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // (q b)^3 per XCD, below 2^40 per graph
     int qmax = 0;
-    int64_t total = 0;
     for (int g : order) {
-        const double qq = q[g], w = descs[g].tile;
-        const int best = (int)(std::min_element(load, load + 8) - load);
+        const int64_t e = (int64_t)q[g] * descs[g].tile;
+        int best = 0;
+        for (int x = 1; x < 8; ++x) best = load[x] < load[best] ? x : best;
         xcd[g] = best;
-        load[best] += qq * qq * qq * w * w * w;
+        load[best] += e * e * e;
         qmax = std::max(qmax, q[g]);
-        total += 1 + (int64_t)q[g] * ((int64_t)q[g] * q[g] - 1);
     }
     // graphs of each width, largest first: those with a round r are a prefix
     std::vector<int> by_width[2];
     for (int g : order) by_width[descs[g].tile == 64 ? 1 : 0].push_back(g);
 
-    items.reserve((size_t)total);
-    std::vector<BatchItem> per[8];
-    for (auto &v : per) v.reserve((size_t)(total / 8 / std::max(1, 2 * qmax + 1) + 16));
-    auto flush = [&](int r, bool close_only) {
-        apsp_batch_plan::Launch L;
-        L.r = r;
-        L.close_only = close_only;
+    // Launch 0 is phase 1 of round 0; launches 2r+1, 2r+2 are phases 2 and 3
+    // of round r.  Items are written in place: first the number of items of
+    // every (launch, XCD) pair, whose prefix sums give each pair's range,
+    // then the items, graph by graph, at their pair's cursor.
+    const int nl = 1 + 2 * qmax;
+    std::vector<int64_t> cnt((size_t)nl * 8, 0);
+    for (int g = 0; g < G; ++g) {
+        const int64_t qg = q[g];
+        int64_t *c = cnt.data() + xcd[g];
+        c[0] += 1;
+        if (qg > 1)
+            for (int64_t r = 0; r < qg; ++r) {
+                c[(2 * r + 1) * 8] += 2 * (qg - 1);
+                c[(2 * r + 2) * 8] += (qg - 1) * (qg - 1);
+            }
+    }
+    std::vector<int64_t> cur((size_t)nl * 8);
+    int64_t pos = 0;
+    p.launches.resize((size_t)nl);
+    for (int l = 0; l < nl; ++l) {
+        auto &L = p.launches[(size_t)l];
+        L.r = l == 0 ? 0 : (l - 1) / 2;
+        L.close_only = l == 0;
         for (int x = 0; x < 8; ++x) {
-            L.ranges.offset[x] = (int32_t)items.size();
-            L.ranges.count[x] = (int32_t)per[x].size();
-            items.insert(items.end(), per[x].begin(), per[x].end());
-            per[x].clear();
+            L.ranges.offset[x] = (int32_t)pos;
+            L.ranges.count[x] = (int32_t)cnt[(size_t)l * 8 + x];
+            cur[(size_t)l * 8 + x] = pos;
+            pos += cnt[(size_t)l * 8 + x];
         }
-        p.launches.push_back(L);
-    };
-    auto push = [&](int g, int I, int J) {
-        BatchItem it;
+    }
+    const int64_t launch_items = pos;
+    int64_t scan_items = 0;
+    if (p.dtype == APSP_I32)
+        for (int g = 0; g < G; ++g) {
+            const int64_t qs = (descs[g].n + kRoundB - 1) / kRoundB;
+            scan_items += qs * qs;
+        }
+    items.resize((size_t)(launch_items + scan_items));
+    BatchItem *out = items.data();
+    auto put = [&](int l, int g, int I, int J) {
+        BatchItem &it = out[cur[(size_t)l * 8 + xcd[g]]++];
         it.graph = g;
         it.ij = (I << 16) | J;
-        per[xcd[g]].push_back(it);
     };
     // Within a launch the longest items go first, where they overlap the
     // rest of the launch instead of its tail: 128-wide before 64-wide, and in
     // phase 3 the diagonal block r+1 (whose workgroup also closes it) first.
     for (int w = 0; w < 2; ++w)
-        for (int g : by_width[w]) push(g, 0, 0);  // phase 1 of round 0, every graph
-    flush(0, true);
+        for (int g : by_width[w]) put(0, g, 0, 0);  // phase 1 of round 0, every graph
     for (int r = 0; r < qmax; ++r) {
+        const int l2 = 2 * r + 1, l3 = 2 * r + 2;
         for (int w = 0; w < 2; ++w)
             for (int g : by_width[w]) {  // phase 2 of round r
                 const int qg = q[g];
                 if (qg <= r) break;  // and every later (smaller) graph of this width
                 if (qg == 1) continue;
                 for (int J = 0; J < qg; ++J)
-                    if (J != r) push(g, r, J);
+                    if (J != r) put(l2, g, r, J);
                 for (int I = 0; I < qg; ++I)
-                    if (I != r) push(g, I, r);
+                    if (I != r) put(l2, g, I, r);
             }
-        flush(r, false);
         for (int w = 0; w < 2; ++w) {  // phase 3 of round r
             for (int g : by_width[w]) {
                 const int qg = q[g];
                 if (qg <= r) break;
-                if (qg > 1 && r + 1 < qg) push(g, r + 1, r + 1);
+                if (qg > 1 && r + 1 < qg) put(l3, g, r + 1, r + 1);
             }
             for (int g : by_width[w]) {
                 const int qg = q[g];
                 if (qg <= r) break;
                 if (qg == 1) continue;
-                for (int I = 0; I < qg; ++I)
+                for (int I = 0; I < qg; ++I) {
+                    if (I == r) continue;
                     for (int J = 0; J < qg; ++J)
-                        if (I != r && J != r && !(I == r + 1 && J == r + 1)) push(g, I, J);
+                        if (J != r && !(I == r + 1 && J == r + 1)) put(l3, g, I, J);
+                }
             }
         }
-        flush(r, false);
     }
     if (p.dtype == APSP_I32) {
-        for (auto &v : per) v.clear();
+        // the weight scan: every 128 x 128 tile of every graph, dealt to the
+        // XCDs in turn
+        int64_t sc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t k = 0; k < scan_items; ++k) ++sc[k & 7];
+        int64_t sp[8];
+        int64_t at = launch_items;
+        for (int x = 0; x < 8; ++x) {
+            p.scan.offset[x] = (int32_t)at;
+            p.scan.count[x] = (int32_t)sc[x];
+            sp[x] = at;
+            at += sc[x];
+        }
         int64_t next = 0;
         for (int g = 0; g < G; ++g) {
             const int qs = (descs[g].n + kRoundB - 1) / kRoundB;
             for (int I = 0; I < qs; ++I)
                 for (int J = 0; J < qs; ++J) {
-                    BatchItem it;
+                    BatchItem &it = out[sp[next++ & 7]++];
                     it.graph = g;
                     it.ij = (I << 16) | J;
-                    per[next++ & 7].push_back(it);
                 }
-        }
-        for (int x = 0; x < 8; ++x) {
-            p.scan.offset[x] = (int32_t)items.size();
-            p.scan.count[x] = (int32_t)per[x].size();
-            items.insert(items.end(), per[x].begin(), per[x].end());
         }
     }
     p.items = (int64_t)items.size();
@@ -256,8 +289,13 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
     p->dtype = dtype;
     p->stream_ordered = stream_ordered;
     p->device = -1;
-    std::vector<apsp::BatchDesc> descs;
-    std::vector<apsp::BatchItem> items;
+    // host tables in per-thread buffers that keep their capacity between
+    // calls (a one-shot solve builds a plan per call)
+    thread_local std::vector<apsp::BatchDesc> descs;
+    thread_local std::vector<apsp::BatchItem> items;
+    thread_local std::vector<unsigned char> host;
+    descs.clear();
+    items.clear();
     if (count > 0) apsp::plan_build(*p, ptrs, ns, lds, count, tile, table, descs, items);
     if (!descs.empty()) {  // an empty batch makes no HIP call at all
         if (hipGetDevice(&p->device) != hipSuccess) {
@@ -265,7 +303,6 @@ int32_t plan_create(void *const *ptrs, const int32_t *ns, const int64_t *lds, in
             return APSP_ERR_DEVICE;
         }
         const TableLayout t = table_layout(descs.size(), items.size(), dtype);
-        std::vector<unsigned char> host;
         pack_tables(descs, items, t, host);
         void *buf = nullptr;
         const hipError_t e =
