@@ -36,6 +36,7 @@
 #include <algorithm>
 
 #include "apsp_tile.h"
+#include "apsp_tilemap.h"
 
 namespace apsp {
 
@@ -44,12 +45,11 @@ namespace {
 using tile::NT;
 using tile::TB;
 
-// Tile sets of the pair launches.
-constexpr int kPanelsSnap = 0;  // phase 2 of round pr, also written to the copy
-constexpr int kNext2 = 1;       // pair pass on block rows/columns r+2, r+3 (outside r, r+1)
-constexpr int kRest2 = 2;       // pair pass on a band of block rows, outside blocks [r, r+2+nxt)
-constexpr int kFix = 3;         // round r+1's deferred update of block row/column r tiles
-constexpr int kNextR = 4;       // round r's phase 3 on block row/column r+1 (direct form only)
+using tilemap::kPanelsSnap;
+using tilemap::kNext2;
+using tilemap::kRest2;
+using tilemap::kFix;
+using tilemap::kNextR;
 
 struct PairArgs {
     uint32_t *D;
@@ -86,97 +86,24 @@ struct Job {
 template <int MODE>
 __device__ __forceinline__ Job job_of(const PairArgs &a) {
     Job j{0, 0, a.r, 2, false, false};
-    const int r = a.r, q = a.q;
+    tilemap::pair_tile_of<MODE>((int)blockIdx.x, a.r, a.q, a.nxt, a.lo, a.hi, a.final_, j.I, j.J);
+    const int r = a.r;
     if (MODE == kPanelsSnap) {
-        // same order as phase 2: block row pr (every column but pr), then
-        // block column pr (every row but pr)
-        int t = blockIdx.x;
-        if (t < q - 1) {
-            j.I = r;
-            j.J = t < r ? t : t + 1;
-        } else {
-            t -= q - 1;
-            j.J = r;
-            j.I = t < r ? t : t + 1;
-        }
         j.kb = r;
         j.kblocks = 1;
         return j;
     }
     if (MODE == kFix) {
-        int t = blockIdx.x;
-        if (!a.final_) {  // (x, r) and (r, x), x = r+2 .. r+1+nxt
-            const int x = r + 2 + (t >> 1);
-            j.I = (t & 1) ? r : x;
-            j.J = (t & 1) ? x : r;
-        } else {
-            // block row r but columns r+1 and the next blocks, then block
-            // column r but rows r, r+1 and the next blocks
-            const int rowpart = q - 1 - a.nxt;
-            if (t < rowpart) {
-                j.I = r;
-                j.J = t < r + 1 ? t : t + 1 + a.nxt;
-            } else {
-                t -= rowpart;
-                j.J = r;
-                j.I = t < r ? t : t + 2 + a.nxt;
-            }
-        }
         j.kb = r + 1;
         j.kblocks = 1;
         return j;
     }
     if (MODE == kNextR) {
-        // block row r+1 (every column but r), then block column r+1 (every
-        // row but r, r+1): the tiles the next round's phases read; the
-        // workgroup of diagonal block r+1 closes it (phase 1 of round r+1)
-        int t = blockIdx.x;
-        if (t < q - 1) {
-            j.I = r + 1;
-            j.J = t < r ? t : t + 1;
-        } else {
-            t -= q - 1;
-            j.J = r + 1;
-            j.I = t < r ? t : t + 2;
-        }
         j.kblocks = 1;
         j.close = a.close && j.I == r + 1 && j.J == r + 1;
         return j;
     }
-    const int m = q - 2;  // blocks outside r, r+1
-    if (MODE == kNext2) {
-        // block rows r+2.. (every column outside r, r+1), then block columns
-        // r+2.. (every row outside r .. r+1+nxt)
-        int t = blockIdx.x;
-        if (t < a.nxt * m) {
-            j.I = r + 2 + t / m;
-            const int c = t % m;
-            j.J = c < r ? c : c + 2;
-        } else {
-            t -= a.nxt * m;
-            const int m2 = m - a.nxt;
-            j.J = r + 2 + t / m2;
-            const int c = t % m2;
-            j.I = c < r ? c : c + 2 + a.nxt;
-        }
-        j.close = a.close && j.I == r + 2 && j.J == r + 2;
-    } else {  // kRest2: rows [lo, hi) and columns outside the excluded blocks [r, e1)
-        const int e1 = r + 2 + a.nxt;
-        const int ex = e1 - r;
-        const int x0 = r > a.lo ? r : a.lo, x1 = e1 < a.hi ? e1 : a.hi;
-        const int skipped = x1 > x0 ? x1 - x0 : 0;
-        const int rows = a.hi - a.lo - skipped;
-        const int mc = q - ex;
-        const int T = rows * mc;
-        const int wg = blockIdx.x;
-        const int x = wg & 7, s = wg >> 3;
-        const int per = T >> 3, rem = T & 7;
-        const int tl = x * per + (x < rem ? x : rem) + s;  // one contiguous run per XCD
-        const int ti = tl / mc, tj = tl - ti * mc;
-        j.I = a.lo + ti;
-        if (skipped && j.I >= x0) j.I += skipped;
-        j.J = tj < r ? tj : tj + ex;
-    }
+    if (MODE == kNext2) j.close = a.close && j.I == r + 2 && j.J == r + 2;
     j.pending = a.prev >= 0 && (j.I == a.prev || j.J == a.prev) && j.I != a.prev + 1 &&
                 j.J != a.prev + 1;
     return j;

@@ -28,6 +28,7 @@
 // rest, which a helper stream runs while the caller's stream goes on with
 // phase 2 of round r+1.  The copies of rounds r and r+1 use two slots.
 #include "apsp_tile.h"
+#include "apsp_tilemap.h"
 
 namespace apsp {
 
@@ -36,11 +37,9 @@ namespace {
 using tile::NT;
 using tile::TB;
 
-enum SymSet {
-    kSymAll = 0,   // every upper tile outside block row/column r, (q-1) q / 2
-    kSymRest = 1,  // outside block rows/columns r and r+1, (q-2) (q-1) / 2
-    kSymNext = 2,  // the upper tiles in block row/column r+1, diagonal first, q-1
-};
+using tilemap::kSymAll;
+using tilemap::kSymNext;
+using tilemap::kSymRest;
 
 // Phase 2 of round r: tiles (r, J), J > r, then (I, r), I < r (q-1 of them),
 // stored in place and into R (row block as is, column block transposed).
@@ -73,42 +72,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
         tile::store_acc_t<Op>(acc, R, ldr, i0, mr, nc);  // columns are k (nc == kw)
 }
 
-// Upper-triangle tile of a phase-3 set: the a <= b entries of the m x m grid
-// of block indices without the `skip` indices r .. r+skip-1, row-major, each
-// XCD (workgroup w runs on XCD w % 8) dealt one contiguous range of them.
-__device__ __forceinline__ void upper_tile(int wg, int r, int q, int skip, int &I, int &J) {
-    const int m = q - skip;
-    const int T = m * (m + 1) / 2;
-    const int x = wg & 7, s = wg >> 3;
-    const int per = T >> 3, rem = T & 7;
-    const int id = x * per + (x < rem ? x : rem) + s;
-    // rows before row a hold start(a) = a m - a (a - 1) / 2 entries
-    auto start = [&](int a) { return a * m - a * (a - 1) / 2; };
-    const double w = 2.0 * m + 1.0;
-    int a = (int)((w - sqrt(w * w - 8.0 * id)) * 0.5);
-    a = a < 0 ? 0 : (a > m - 1 ? m - 1 : a);
-    while (a + 1 < m && start(a + 1) <= id) ++a;
-    while (a > 0 && start(a) > id) --a;
-    const int b = a + (id - start(a));
-    I = a < r ? a : a + skip;
-    J = b < r ? b : b + skip;
-}
-
-template <int SET>
-__device__ __forceinline__ void sym_tile_of(int wg, int r, int q, int &I, int &J) {
-    if (SET == kSymNext) {
-        if (wg < q - 1 - r) {  // (r+1, r+1) first: its closure is the chain
-            I = r + 1;
-            J = r + 1 + wg;
-        } else {
-            I = wg - (q - 1 - r);
-            J = r + 1;
-        }
-    } else {
-        upper_tile(wg, r, q, SET == kSymRest ? 2 : 1, I, J);
-    }
-}
-
 // Phase 3 on a tile set from R.  DIRECT: n a multiple of 128 and D's rows
 // 16-byte aligned, every tile full; both operands staged straight into LDS.
 // Otherwise the register-staged loader reads A transposed from R with the
@@ -119,7 +82,7 @@ __device__ __forceinline__ void sym_update(uint32_t *D, int64_t ld, int64_t n, i
                                            int vec, const uint32_t *R, int64_t ldr, int close,
                                            tile::Lds &L) {
     int I, J;
-    sym_tile_of<SET>(blockIdx.x, r, q, I, J);
+    tilemap::sym_tile_of<SET>((int)blockIdx.x, r, q, I, J);
     const int64_t i0 = (int64_t)I * TB, j0 = (int64_t)J * TB, kb = (int64_t)r * TB;
     const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
     const int mr = (int)((n - i0) < TB ? (n - i0) : TB);

@@ -160,21 +160,27 @@ def test_stream_state_released_with_the_stream(apsp):
     import torch
 
     dev = torch.device("cuda:0")
-    base = apsp.stream_state_count()
     n = 300
     u, v, w = gg.swiss_roll_knn(n, gg.CFG_TEST, 990)
     W = gg.dense_from_edges(n, u, v, w, np.int32)
     ref = oracle.fw(W)
     for i in range(5):
+        # torch hands out streams from a pool: this one may carry state from
+        # earlier solves, so release it first
         s = torch.cuda.Stream(dev)
+        apsp.release_stream_state(s)
+        base = apsp.stream_state_count()
         D = torch.from_numpy(W).to(dev)
         apsp.solve(D, stream=s)          # int32: keeps the scan word per stream
         assert apsp.stream_state_count() == base + 1
         apsp.release_stream_state(s)
         assert apsp.stream_state_count() == base
         assert np.array_equal(D.cpu().numpy().astype(np.int64), ref)
-    apsp.release_stream_state(torch.cuda.Stream(dev))  # no state: a no-op
-    assert apsp.stream_state_count() == base
+    s = torch.cuda.Stream(dev)
+    apsp.release_stream_state(s)
+    before = apsp.stream_state_count()
+    apsp.release_stream_state(s)  # no state left: a no-op
+    assert apsp.stream_state_count() == before
     # round pairs at width 128 from 3 rounds: the copies come with the state
     prev_w = apsp.set_width64_max_n(0)
     prev_p = apsp.set_round_pair_threshold(3)
@@ -185,6 +191,8 @@ def test_stream_state_released_with_the_stream(apsp):
         want = apsp.stream_state_bytes(n, apsp.APSP_F32)
         assert want == 256 + 8 * 128 * 2048 * 4
         s = torch.cuda.Stream(dev)
+        apsp.release_stream_state(s)
+        base = apsp.stream_state_count()
         torch.cuda.synchronize()
         apsp.solve(D, stream=s)
         torch.cuda.synchronize()
