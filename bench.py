@@ -58,7 +58,8 @@ TRAFFIC_FILE = os.path.join(PROFILES, "traffic_phase3_swiss16384_f32.txt")
 # the phase-3 kernel and the schedule that launches it (the traffic figures
 # hold while these sources are unchanged)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_04446_amd", "csrc", f)
-                  for f in ("apsp_plain.hip", "apsp_pair.hip", "apsp_tile.h", "apsp_runtime.hip")]
+                  for f in ("apsp_plain.hip", "apsp_pair.hip", "apsp_tile.h", "apsp_tilemap.h",
+                            "apsp_runtime.hip")]
 
 
 def cell_updates_per_s(n: int, seconds: float) -> float:
@@ -639,6 +640,47 @@ def rest_roofline(phases: dict, K: int, n: int, b: int) -> dict:
     }
 
 
+def bench_small(apsp, torch, dev, sizes=(256, 1024, 2048, 4096), reps: int = 20) -> dict:
+    """Single solves of small Swiss-roll kNN graphs (fp32, matrix resident):
+    median solve time at the library's round width (64 up to n = 5120) and,
+    for comparison, with rounds of 128."""
+    import numpy as np
+
+    import graphgen as gg
+
+    out = {}
+    for n in sizes:
+        u, v, w = gg.swiss_roll_knn(n, gg.CFG_SERVING, 10 * n)
+        P = gg.device_dense_from_edges(n, u, v, w, np.float32, dev)
+        X = torch.empty_like(P)
+        res = {"round_width": apsp.round_width(n, apsp.APSP_F32)}
+        for label, lim in (("ms", None), ("width128_ms", 0)):
+            prev = apsp.set_width64_max_n(lim) if lim is not None else None
+            try:
+                ts = []
+                for i in range(reps + 2):
+                    X.copy_(P)
+                    a = torch.cuda.Event(enable_timing=True)
+                    e = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    apsp.solve(X)
+                    e.record()
+                    torch.cuda.synchronize()
+                    if i >= 2:
+                        ts.append(a.elapsed_time(e))
+            finally:
+                if prev is not None:
+                    apsp.set_width64_max_n(prev)
+            res[label] = round(sorted(ts)[len(ts) // 2], 4)
+        res["T_cell_updates_per_s"] = round(float(n) ** 3 / (res["ms"] * 1e-3) / 1e12, 3)
+        out[str(n)] = res
+        log(f"small: n={n} {res['ms']} ms at width {res['round_width']} "
+            f"({res['width128_ms']} ms at 128)")
+        del P, X
+    return {"workload": "Swiss-roll kNN (k=10, union), fp32; median of "
+                        f"{reps} solves, HIP events around apsp_solve", "sizes": out}
+
+
 def bench_long(apsp, torch, dev, n: int = 65536) -> dict:
     """One full solve of the n = 65536 Swiss-roll kNN workload (16 GiB fp32
     matrix, 512 rounds): whole-solve throughput and per-phase times."""
@@ -690,6 +732,8 @@ def main() -> int:
                     help="one full n=65536 solve with per-phase times (0 disables it)")
     ap.add_argument("--stretch-rounds", type=int, default=4,
                     help="timed rounds of the n=262144 solve (0 disables it)")
+    ap.add_argument("--small", type=int, default=1,
+                    help="single solves of n = 256 .. 4096 (0 disables them)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -758,6 +802,8 @@ def main() -> int:
     if args.variants:
         variants = bench_variants(apsp, torch, dev, pristine, work, n, b)
 
+    small = bench_small(apsp, torch, dev) if args.small else None
+
     batched = None
     if args.batched > 0:
         batched = bench_batched(apsp, torch, dev, args.batched, reps=3,
@@ -807,6 +853,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "valu_probe": probe,
         "variants": variants,
+        "small_solves": small,
         "batched": batched,
         "serving": serving,
         "long_run": long_run,
