@@ -75,7 +75,10 @@ enum {
  * Rounds are 64 wide up to n = 5120 and 128 wide above (apsp_round_width).
  * From 3 rounds on (64 rounds of width 64) the phases of round r+1 overlap the bulk of round r's phase 3
  * on library-owned helper streams (one set per device and caller stream,
- * created on first use and kept until apsp_release_stream_state; from 64
+ * created on first use and kept until apsp_release_stream_state: a chain
+ * stream, which waits for `stream`'s earlier work and runs the chain of
+ * phases, and two band streams, created one after the other so that HIP
+ * deals them to three different hardware queues; from 64
  * rounds up that phase 3 runs as two
  * bands of block rows on two of them); the call makes `stream` wait for that
  * work, so stream order is preserved.  int32 matrices are first scanned for
@@ -119,7 +122,7 @@ int32_t apsp_set_round_pair_threshold(int32_t rounds);
 /*
  * Per-stream state.  apsp_solve, apsp_solve_rounds, apsp_solve_profiled and
  * apsp_solve_symmetric keep, per (device, caller stream), the state
- * apsp_solve describes: two helper streams, three events, the 256-byte scan
+ * apsp_solve describes: three helper streams, five events, the 256-byte scan
  * word and, once a solve ran round pairs or a symmetric solve of 2 or more
  * rounds ran, the panel copies.  int32 solves and solves long enough for the
  * lookahead create it; it lives until released here or the process ends.

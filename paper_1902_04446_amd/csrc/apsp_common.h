@@ -274,13 +274,14 @@ int64_t set_pair_rounds(int64_t rounds);
 int64_t stream_state_bytes(int64_t n, int dtype);
 int64_t stream_state_count();
 hipError_t release_stream_state(hipStream_t s);
-// Part of that state lent to the symmetric solver: the first helper stream of
-// caller stream s on the current device, two events and the first two
-// row-copy slots (128 x ld words each, ld = 128 ceil(n / 128)), created on
-// first use.  On hipSuccess *lock holds the state's enqueue lock.
+// Part of that state lent to the symmetric solver: the chain stream and the
+// first helper stream of caller stream s on the current device, four events
+// and the first two row-copy slots (128 x ld words each, ld = 128 ceil(n /
+// 128)), created on first use.  On hipSuccess *lock holds the state's
+// enqueue lock.
 struct SideResources {
-    hipStream_t side;
-    hipEvent_t p2_done, rest_done;
+    hipStream_t chain, side;
+    hipEvent_t enter, leave, p2_done, rest_done;
     uint32_t *slot[2];
     int64_t ld;
 };

@@ -84,7 +84,15 @@ constexpr int64_t kDefaultWidth64MaxN = 5120;
 std::atomic<int64_t> g_w64_max_n{kDefaultWidth64MaxN};
 
 struct Helper {
+    // The solve's own streams: `chain` runs what the caller's stream would
+    // (it starts after the caller's earlier work and the caller waits for
+    // it), side[g] run the bands.  They are created together, one after the
+    // other: HIP deals streams to its hardware queues (4 by default) in
+    // creation order, so the three land on three different queues and the
+    // bands overlap the chain whatever queue the caller's stream is on.
+    hipStream_t chain = nullptr;
     hipStream_t side[kBands] = {};
+    hipEvent_t enter = nullptr, leave = nullptr;  // caller -> chain, chain -> caller
     hipEvent_t p2_done = nullptr;             // recorded on S after P2(r)
     hipEvent_t rest_done[kBands] = {};        // recorded on H_g after band g of B(r)
     uint32_t *word = nullptr;                 // int32: largest finite entry of the matrix
@@ -113,6 +121,7 @@ bool ensure_copies(Helper *h, int64_t n, hipStream_t s) {
         if (h->copies_buf) {
             // earlier solves on these streams may still read the old buffer
             if (hipStreamSynchronize(s) != hipSuccess) return false;
+            if (h->chain && hipStreamSynchronize(h->chain) != hipSuccess) return false;
             for (hipStream_t x : h->side)
                 if (hipStreamSynchronize(x) != hipSuccess) return false;
             (void)hipFree(h->copies_buf);
@@ -153,12 +162,15 @@ Helper *helper_for(hipStream_t s, hipError_t *err) {
     if (it != g_helpers.end()) return it->second;
     Helper *h = new Helper();
     const char *what = "hipStreamCreateWithFlags";
+    e = hipStreamCreateWithFlags(&h->chain, hipStreamNonBlocking);
     for (int g = 0; g < kBands && e == hipSuccess; ++g)
         e = hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking);
     if (e == hipSuccess) {
         what = "hipEventCreateWithFlags";
         e = hipEventCreateWithFlags(&h->p2_done, hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->enter, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->leave, hipEventDisableTiming);
     for (int g = 0; g < kBands && e == hipSuccess; ++g)
         e = hipEventCreateWithFlags(&h->rest_done[g], hipEventDisableTiming);
     if (e == hipSuccess) {
@@ -178,8 +190,11 @@ Helper *helper_for(hipStream_t s, hipError_t *err) {
 // Destroy a helper's streams and events and free its device memory (its
 // work must have finished).
 void destroy_helper(Helper *h) {
+    if (h->chain) (void)hipStreamDestroy(h->chain);
     for (hipStream_t x : h->side)
         if (x) (void)hipStreamDestroy(x);
+    if (h->enter) (void)hipEventDestroy(h->enter);
+    if (h->leave) (void)hipEventDestroy(h->leave);
     if (h->p2_done) (void)hipEventDestroy(h->p2_done);
     for (hipEvent_t e : h->rest_done)
         if (e) (void)hipEventDestroy(e);
@@ -248,6 +263,9 @@ hipError_t side_resources(hipStream_t s, int64_t n, SideResources *out,
         note_message("the symmetric solve's row-panel copies could not be allocated");
         return hipErrorOutOfMemory;
     }
+    out->chain = h->chain;
+    out->enter = h->enter;
+    out->leave = h->leave;
     out->side = h->side[0];
     out->p2_done = h->p2_done;
     out->rest_done = h->rest_done[0];
@@ -279,6 +297,7 @@ hipError_t release_stream_state(hipStream_t s) {
         // kernels on `s` read the word and the copies; the helper streams'
         // kernels too
         e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->chain);
         for (hipStream_t x : h->side)
             if (e == hipSuccess) e = hipStreamSynchronize(x);
         if (e != hipSuccess) {
@@ -293,7 +312,8 @@ hipError_t release_stream_state(hipStream_t s) {
 }
 
 hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0, int64_t r1,
-                      bool prologue, hipStream_t s, PhaseTimes *times) {
+                      bool prologue, hipStream_t caller, PhaseTimes *times) {
+    hipStream_t s = caller;  // S: the caller's stream, or the helper's chain stream
     // Round width: 64 for small matrices (apsp_small.hip), else 128.
     const int b = round_width(n);
     const bool w64 = b != kRoundB;
@@ -319,6 +339,16 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     // that a pair has no rest set anyway), whatever the threshold.
     const bool pairs = !w64 && lookahead && q >= g_pair_rounds.load() && r1 - r0 >= 2 &&
                        ensure_copies(h, n, s);
+    if (lookahead) {
+        // S = the chain stream, after the caller's earlier work
+        hipError_t e = hipEventRecord(h->enter, caller);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->chain, h->enter, 0);
+        if (e != hipSuccess) {
+            note_error("entering the solve's streams", e);
+            return e;
+        }
+        s = h->chain;
+    }
     // the phase launches at this width
     auto phase1 = [&](int64_t r) {
         return w64 ? launch_phase1_64(D, n, ld, dtype, r, s) : launch_phase1(D, n, ld, dtype, r, s);
@@ -545,6 +575,10 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             }
         }
         wait_rest(s);
+    }
+    if (s != caller) {  // the caller's stream waits for S (which waited for every band)
+        chk(hipEventRecord(h->leave, s));
+        chk(hipStreamWaitEvent(caller, h->leave, 0));
     }
     if (err != hipSuccess) return err;
     if (!times) return hipSuccess;

@@ -203,8 +203,9 @@ struct SymLaunch {
 
 }  // namespace
 
-hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s) {
+hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t caller) {
     if (n <= 0) return hipSuccess;
+    hipStream_t s = caller;  // the caller's stream, then the state's chain stream
     const int nb = (int)((n + 63) / 64);
     const dim3 mgrid((unsigned)((int64_t)nb * (nb + 1) / 2));
     auto mirror = [&]() {
@@ -220,8 +221,14 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
 
     SideResources res;
     std::unique_lock<std::mutex> lock;
-    e = side_resources(s, n, &res, &lock);
+    e = side_resources(caller, n, &res, &lock);
     if (e != hipSuccess) return e;
+    // the rounds run on the chain stream (after the caller's earlier work) and
+    // the helper stream, which sit on different hardware queues
+    e = hipEventRecord(res.enter, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(res.chain, res.enter, 0);
+    if (e != hipSuccess) return e;
+    s = res.chain;
     SymLaunch L;
     L.D = D;
     L.ld = ld;
@@ -232,7 +239,7 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
     // full tiles, aligned rows, 32-bit lane offsets (128 ld and 128 ldr < 2^30)
     L.direct = n % TB == 0 && L.vec && ld < ((int64_t)1 << 22) && res.ld < ((int64_t)1 << 22);
 
-    if (q == 2) {  // no rest set to overlap: round by round on the caller's stream
+    if (q == 2) {  // no rest set to overlap: round by round on the chain stream
         for (int r = 0; r < q && e == hipSuccess; ++r) {
             uint32_t *R = res.slot[r & 1];
             e = L.panels(r, R, res.ld, s);
@@ -241,7 +248,7 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
     } else {
         // round r: phase 2 (phase 1 ran fused in the previous round's next
         // set), then the rest set on the helper stream once phase 2 is done,
-        // and the next set on the caller's stream after the previous round's
+        // and the next set on the chain stream after the previous round's
         // rest set (it rewrites tiles in block row/column r+1, which that set
         // wrote); the previous rest set also read the copy slot that phase 2
         // of round r+1 overwrites, which that same wait orders.
@@ -262,6 +269,9 @@ hipError_t run_symmetric(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStrea
         }
     }
     if (e == hipSuccess) e = mirror();  // blocks below the diagonal were not updated
+    // the caller's stream waits for the chain, which waited for the helper
+    if (e == hipSuccess) e = hipEventRecord(res.leave, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(caller, res.leave, 0);
     if (e != hipSuccess) note_error("symmetric solve launch", e);
     return e;
 }
