@@ -607,10 +607,10 @@ def rest_roofline(phases: dict, K: int, n: int, b: int) -> dict:
     pair_upd, pair_launches = phase3_pair_updates(n, b)
     launches = phases["phase3_rest_launches"] / K
     if q >= 3 and launches == pair_launches:
-        kernel = ("k_pair<kRest2> (phase 3 of a pair of rounds in one pass, k over two "
-                  "blocks, outside block rows/columns r .. r+3; 128x128 tiles; two concurrent "
-                  "launches per pair, one per band of block rows; per-launch figures are per "
-                  "pair of rounds)")
+        kernel = ("k_pair_rest_direct, kRest2 (phase 3 of a pair of rounds in one pass, k "
+                  "over two blocks, outside block rows/columns r .. r+3; 128x128 tiles, "
+                  "operands staged straight into LDS; two concurrent launches per pair, one "
+                  "per band of block rows; per-launch figures are per pair of rounds)")
         launch_s = phases["phase3_rest"] / K / 1e3 / pair_launches
         per_launch = pair_upd / pair_launches
     elif q >= 3 and launches == rest_launches:
