@@ -209,6 +209,11 @@ hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
 int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 // Whether launch_pair_rest takes the direct-staged kernel for this matrix.
 bool pair_rest_direct(const uint32_t *D, int64_t n, int64_t ld, int dtype);
+// A single round's rest set on block rows [lo, hi) (outside block rows/columns
+// r, r+1), direct-staged: fp32, pair_rest_direct(D, ...) true, the column
+// panel of round r transposed in c.colT[col_slot] (launch_pair_panels).
+hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int64_t r, int64_t lo,
+                                   int64_t hi, const PairCopies &c, int col_slot, hipStream_t s);
 // Round r+1's deferred phase-3 update on block row/column r: !final_: tiles
 // (x, r), (r, x) for the next blocks x; final_: every other one but the
 // blocks r+1.

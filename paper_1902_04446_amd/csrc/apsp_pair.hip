@@ -50,6 +50,7 @@ using tilemap::kNext2;
 using tilemap::kRest2;
 using tilemap::kFix;
 using tilemap::kNextR;
+using tilemap::kRest1;
 
 struct PairArgs {
     uint32_t *D;
@@ -95,6 +96,10 @@ __device__ __forceinline__ Job job_of(const PairArgs &a) {
     }
     if (MODE == kFix) {
         j.kb = r + 1;
+        j.kblocks = 1;
+        return j;
+    }
+    if (MODE == kRest1) {
         j.kblocks = 1;
         return j;
     }
@@ -186,6 +191,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     PairArgs a) {
     __shared__ tile::Lds L;
     pair_direct_update<kRest2>(a, L);
+}
+
+// A single round's rest set (kRest1) in the same direct form, for matrices
+// solved in single rounds: the column panel from its transposed copy.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_round_rest_direct(
+    PairArgs a) {
+    __shared__ tile::Lds L;
+    pair_direct_update<kRest1>(a, L);
 }
 
 // kNext2 and kNextR (with the closure's registers: at most 152, 3 workgroups
@@ -325,6 +338,19 @@ hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
         return hipGetLastError();
     }
     return launch<kRest2>(a, dtype, wmax, (unsigned)count, s);
+}
+
+hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int64_t r, int64_t lo,
+                                   int64_t hi, const PairCopies &c, int col_slot, hipStream_t s) {
+    const int64_t count = tilemap::tile_count(num_rounds(n), r, kRest, lo, hi);
+    if (count <= 0) return hipSuccess;
+    PairArgs a = base_args(D, n, ld, (int)r, c);
+    a.lo = (int)lo;
+    a.hi = (int)hi;
+    a.at0 = c.colT[col_slot];
+    a.at1 = a.at0;
+    hipLaunchKernelGGL(k_round_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_fix(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,

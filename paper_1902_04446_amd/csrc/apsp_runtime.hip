@@ -217,6 +217,14 @@ bool uses_pairs(int64_t n) {
     return b == kRoundB && uses_lookahead(n) && q >= g_pair_rounds.load() && q >= 2;
 }
 
+// Whether a full solve of an fp32 matrix of n vertices runs single rounds of
+// 128 with the direct-staged rest set (which needs the transposed column
+// copies), given 16-byte aligned rows.
+bool uses_direct_single(int64_t n, int dtype) {
+    return dtype == 1 && n % kRoundB == 0 && round_width(n) == kRoundB && uses_lookahead(n) &&
+           !uses_pairs(n);
+}
+
 // Timing events of one profiled solve.
 struct Timer {
     std::vector<hipEvent_t> ev;
@@ -245,7 +253,8 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 
 int64_t stream_state_bytes(int64_t n, int dtype) {
     if (n <= 0 || !(uses_lookahead(n) || dtype == 0)) return 0;
-    return 256 + (uses_pairs(n) ? (int64_t)pair_copies_bytes(n) : 0);
+    return 256 + (uses_pairs(n) || uses_direct_single(n, dtype) ? (int64_t)pair_copies_bytes(n)
+                                                                 : 0);
 }
 
 int64_t stream_state_count() {
@@ -339,6 +348,13 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     // that a pair has no rest set anyway), whatever the threshold.
     const bool pairs = !w64 && lookahead && q >= g_pair_rounds.load() && r1 - r0 >= 2 &&
                        ensure_copies(h, n, s);
+    // Single rounds of 128 on an aligned fp32 matrix: phase 2 also writes its
+    // block column transposed (two slots, rounds alternating), and round r's
+    // phase 3 reads it with both operands staged straight into LDS.  The next
+    // writer of a slot is phase 2 of round r+2, which follows the wait for
+    // round r's rest set on S.
+    const bool direct1 = !w64 && lookahead && !pairs && pair_rest_direct(D, n, ld, dtype) &&
+                         ensure_copies(h, n, s);
     if (lookahead) {
         // S = the chain stream, after the caller's earlier work
         hipError_t e = hipEventRecord(h->enter, caller);
@@ -427,7 +443,10 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         close(sp, s);
         diag_closed = false;
         sp = open(2, s);
-        chk(tile_set(r, kPanels, false));
+        if (direct1)
+            chk(launch_pair_panels(D, n, ld, dtype, r, h->copies, -1, (int)(r & 1), s, wmax));
+        else
+            chk(tile_set(r, kPanels, false));
         close(sp, s);
     };
 
@@ -537,7 +556,11 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 chk(hipEventRecord(h->p2_done, s));
                 wait_rest(s);
                 size_t sp = open(7, s);
-                chk(tile_set(r, kNext, fuse));
+                if (direct1 && fuse)  // (the direct form always closes block r+1)
+                    chk(launch_pair_round_next(D, n, ld, dtype, r, h->copies, (int)(r & 1), s,
+                                               wmax));
+                else
+                    chk(tile_set(r, kNext, fuse));
                 close(sp, s);
                 diag_closed = fuse;
                 for (int g = 0; g < bands; ++g) {
@@ -556,7 +579,11 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                     band_range(g, lo, hi);
                     chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                     const size_t b = open(5, h->side[g]);
-                    chk(rest_rows(r, lo, hi, h->side[g]));
+                    if (direct1)
+                        chk(launch_round_rest_direct(D, n, ld, r, lo, hi, h->copies, (int)(r & 1),
+                                                     h->side[g]));
+                    else
+                        chk(rest_rows(r, lo, hi, h->side[g]));
                     close(b, h->side[g]);
                     chk(hipEventRecord(h->rest_done[g], h->side[g]));
                 }

@@ -84,16 +84,21 @@ __host__ __device__ inline void tile_of(int wg, int r, int q, int row_lo, int ro
 //                rows r, r+1 and those x;
 //   kNextR       round r's phase 3 on block row r+1 (every column but r),
 //                then block column r+1 (every row but r, r+1).
+//   kRest1       a single round's phase 3 on block rows [lo, hi) outside block
+//                rows/columns r, r+1: the band map of kRest above.
 constexpr int kPanelsSnap = 0;
 constexpr int kNext2 = 1;
 constexpr int kRest2 = 2;
 constexpr int kFix = 3;
 constexpr int kNextR = 4;
+constexpr int kRest1 = 5;
 
 template <int MODE>
 __host__ __device__ inline void pair_tile_of(int t, int r, int q, int nxt, int lo, int hi,
                                              int final_, int &I, int &J) {
-    if (MODE == kPanelsSnap) {
+    if (MODE == kRest1) {
+        tile_of<kRest>(t, r, q, lo, hi, I, J);
+    } else if (MODE == kPanelsSnap) {
         if (t < q - 1) {
             I = r;
             J = t < r ? t : t + 1;

@@ -2,10 +2,13 @@
 
 Requests (one graph each, of any size) arrive over time.  The server:
 
-* admits a request when its matrix fits the HBM budget next to the matrices
-  already resident and a slot (a HIP stream) is free: first fit in arrival
-  order, except that a request passed over ``max_bypass`` times blocks the
-  ones behind it, so large requests cannot starve;
+* admits a request when its matrix (and checkpoint buffers) fit the HBM
+  budget next to what is already resident and a slot (a HIP stream) is free:
+  first fit in arrival order, except that a request passed over
+  ``max_bypass`` times blocks the ones behind it, so large requests cannot
+  starve.  The solver state a slot's stream keeps (helper streams' word and
+  panel copies, which grow with the largest request the slot solved and
+  outlive each request) is counted too, as it grows;
 * keeps each admitted matrix in device memory from ingestion to completion;
 * solves in slices of ``slice_rounds`` rounds of the blocked method
   (``apsp_solve_rounds``), at most ``inflight`` slices per request enqueued
@@ -101,6 +104,9 @@ class SimBackend:
     def bytes_needed(self, n: int, checkpoints: int = 0) -> int:
         return 4 * n * n * (1 + checkpoints)
 
+    def state_bytes(self, n: int) -> int:
+        return 0
+
     def num_rounds(self, n: int) -> int:
         return -(-n // self.b) if n else 0
 
@@ -162,11 +168,6 @@ class GpuBackend:
     caller's and no longer counted against the server's budget.
     """
 
-    # per-stream solver state above this many bytes (the round-pair panel
-    # copies) is released when the request that needed it leaves its slot,
-    # so that the admission budget's count of it stays true
-    STATE_KEEP_BYTES = 1 << 20
-
     def __init__(self, device=None, slots: int = 4, dtype: str = "f32", keep_results=True,
                  fail_at: dict = None):
         import torch
@@ -195,9 +196,14 @@ class GpuBackend:
         self._staging = [dict() for _ in range(slots)]
 
     def bytes_needed(self, n: int, checkpoints: int = 0) -> int:
-        """Device bytes a request holds while admitted: its matrix, its
-        checkpoint buffers and the solver's per-stream state for its size."""
-        return 4 * n * n * (1 + checkpoints) + self.apsp.stream_state_bytes(n, self.code)
+        """Device bytes a request holds while admitted: its matrix and its
+        checkpoint buffers."""
+        return 4 * n * n * (1 + checkpoints)
+
+    def state_bytes(self, n: int) -> int:
+        """Device bytes of the solver's state that a slot stream keeps once it
+        has solved an n-vertex request (kept with the slot, grown, not shrunk)."""
+        return self.apsp.stream_state_bytes(n, self.code)
 
     def num_rounds(self, n: int) -> int:
         return self.apsp.num_rounds(n, self.code)
@@ -220,10 +226,7 @@ class GpuBackend:
         return self._empty(req.n, slot)
 
     def free(self, handle, req: Request, slot: int):
-        # the matrix is dropped with its last reference (torch's caching
-        # allocator reuses it); large per-stream state is released
-        if self.apsp.stream_state_bytes(req.n, self.code) > self.STATE_KEEP_BYTES:
-            self.apsp.release_stream_state(self.streams[slot])
+        pass  # dropped with the last reference (torch's caching allocator reuses it)
 
     def close(self):
         """Release the solver state of every slot stream (waits for them)."""
@@ -340,6 +343,9 @@ class ApspServer:
         self.active: list = []
         self.finished: list = []
         self.used = 0
+        # the solver state each slot's stream keeps (counted in `used` while
+        # the server lives: it outlasts the requests that grew it)
+        self.slot_state = [0] * slots
         self.free_slots = list(range(slots))
 
     # ---------------------------------------------------------------- API
@@ -348,7 +354,7 @@ class ApspServer:
         return self.backend.bytes_needed(n, 2 if self.checkpoint_rounds else 0)
 
     def submit(self, req: Request):
-        if self.need(req.n) > self.budget:
+        if self.need(req.n) + self.backend.state_bytes(req.n) > self.budget:
             req.status = "rejected"
             req.error = "matrix larger than the HBM budget"
             self.finished.append(req)
@@ -449,9 +455,13 @@ class ApspServer:
             if req.arrival > now or not self.free_slots:
                 break
             need = self.need(req.n)
-            if self.used + need <= self.budget and not blocked:
+            slot = self.free_slots[0]
+            grow = max(0, self.backend.state_bytes(req.n) - self.slot_state[slot])
+            if self.used + need + grow <= self.budget and not blocked:
                 self.pending.remove(req)
                 req.slot = self.free_slots.pop(0)
+                self.slot_state[slot] += grow
+                self.used += grow
                 req.handle = self.backend.alloc(req, req.slot)
                 self.used += need
                 req.rounds = self.backend.num_rounds(req.n)

@@ -1031,6 +1031,36 @@ def test_symmetric_variant_direct_and_lookahead_vs_oracle(apsp, dev, n, pad):
             assert np.array_equal(got, oracle.blocked(W, 128)), n
 
 
+@pytest.mark.parametrize("n", [384, 1024, 2048])
+def test_single_rounds_direct_rest_vs_oracle(apsp, dev, n):
+    """fp32, rounds of 128 below the pair threshold, n % 128 == 0 and aligned
+    rows: phase 2 writes the transposed column copy and the rest set and the
+    next-row/column set read it (direct staging).  Whole solves, and a solve
+    split into slices (a slice that stops after round r does not fuse block
+    r+1's closure), equal the oracle's blocked model at width 128 bit for bit;
+    unaligned rows (register-staged) too."""
+    import torch
+
+    W, _ = _swiss(n, 9300 + n)
+    ref = oracle.blocked(W, 128)
+    prev = apsp.set_width64_max_n(0)
+    try:
+        q = apsp.num_rounds(n)
+        for pad in (0, 1):
+            view, _ = _to_dev(W, dev, ld=n + pad)
+            apsp.solve(view)
+            torch.cuda.synchronize()
+            assert np.array_equal(view.cpu().numpy(), ref), (n, pad)
+        view, _ = _to_dev(W, dev)
+        cuts = sorted({0, 1, q // 2, q - 1, q})
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            apsp.solve_rounds(view, a, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(view.cpu().numpy(), ref), (n, "slices")
+    finally:
+        apsp.set_width64_max_n(prev)
+
+
 def test_symmetric_variant_equals_full_solve_large(apsp, dev):
     """n = 4096 (32 rounds, direct staging, lookahead): the upper-triangle
     solve gives the full solve's bits at width 128 (checked against the

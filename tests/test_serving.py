@@ -251,3 +251,26 @@ def test_percentile_nearest_rank():
     assert percentile(v, 99) == 99
     assert percentile(v, 100) == 100
     assert percentile([3.0], 99) == 3.0
+
+
+def test_slot_state_is_counted_once_per_slot():
+    """A backend whose slots keep solver state (growing with the largest
+    request they solved): admission counts the growth, the state stays
+    counted after the request leaves, and a request that cannot fit with its
+    state is rejected."""
+    class StateSim(SimBackend):
+        def state_bytes(self, n):
+            return 1000 * n
+
+    clock = Clock()
+    be = StateSim(rate=1e12, clock=clock)
+    budget = be.bytes_needed(512) + 1000 * 512 + 10
+    srv = ApspServer(be, hbm_budget=budget, slots=1, slice_rounds=2, clock=clock)
+    reqs = mk([512, 256, 512])
+    peak, _ = drive(srv, clock, reqs)
+    assert all(r.status == "done" for r in reqs)
+    assert peak <= budget
+    assert srv.slot_state == [1000 * 512] and srv.used == 1000 * 512
+    srv2 = ApspServer(be, hbm_budget=be.bytes_needed(512) + 10, slots=1, clock=clock)
+    r = srv2.submit(Request(rid=9, n=512, arrival=0.0))
+    assert r.status == "rejected"
