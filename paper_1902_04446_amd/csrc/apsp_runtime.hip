@@ -49,7 +49,13 @@ namespace {
 // stream: band g of round r+1 follows band g of round r and needs nothing
 // else of B(r), so one band's launch boundary overlaps the other band's work
 // instead of draining the GPU once per round.
-constexpr int kBands = 2;
+// Measured: three bands (with the chain stream, four library streams on the
+// four hardware queues) lose to two: 121 against 117 ms at n = 16384, 17.5
+// against 16.7 ms at n = 8192.
+#ifndef APSP_BANDS
+#define APSP_BANDS 2
+#endif
+constexpr int kBands = APSP_BANDS;
 // Below this many rounds a band launch is too short for the overlap to pay
 // for the extra launch and event per round; B(r) then runs as one launch.
 #ifndef APSP_MIN_BAND_ROUNDS
