@@ -73,15 +73,15 @@ enum {
  *   dtype  APSP_I32 or APSP_F32.
  *   stream hipStream_t to enqueue on (NULL = default stream).
  * Rounds are 64 wide up to n = 5120 and 128 wide above (apsp_round_width).
- * From 3 rounds on (64 rounds of width 64) the phases of round r+1 overlap the bulk of round r's phase 3
- * on library-owned helper streams (one set per device and caller stream,
- * created on first use and kept until apsp_release_stream_state: a chain
- * stream, which waits for `stream`'s earlier work and runs the chain of
- * phases, and two band streams, created one after the other so that HIP
- * deals them to three different hardware queues; from 64
- * rounds up that phase 3 runs as two
- * bands of block rows on two of them); the call makes `stream` wait for that
- * work, so stream order is preserved.  int32 matrices are first scanned for
+ * From 3 rounds of 128 on (64 rounds of 64) the phases of round r+1 overlap
+ * the bulk of round r's phase 3 on library-owned streams (one set per device
+ * and caller stream, created on first use and kept until
+ * apsp_release_stream_state): a chain stream, which waits for `stream`'s
+ * earlier work and runs the chain of phases, and two band streams, created
+ * one after the other so that HIP deals the three to different hardware
+ * queues; from 64 rounds up that phase 3 runs as two bands of block rows on
+ * the band streams.  The call makes `stream` wait for all of that work, so
+ * stream order is preserved.  int32 matrices are first scanned for
  * their largest finite entry w; when 2 (n-1) w < 2^24 every sum the method
  * forms is an integer below 2^24, and the tiles are computed in fp32
  * arithmetic (exact, so the result is the same) at its higher issue rate.
@@ -90,13 +90,15 @@ enum {
  * phase 3 runs in pairs of rounds: one pass per tile with k over both rounds' blocks, the second
  * round's update of the first round's block row and column deferred and
  * applied from a copy of its panels (the result is the same, bit for bit).
- * Phase 2 of every round also writes its block column transposed, which the
- * bulk of phase 3 reads for fp32 matrices with n a multiple of 128 and
- * 16-byte aligned rows.  The copies take 8 x 128 x 128q x 4 bytes (64 MiB at
- * n = 16384, 1 GiB at n = 262144), allocated with the helper streams on
- * first need and grown for a larger n; growing synchronises `stream` and the
- * helper streams inside the call (solves still running on them may read the
- * old copies).  When they cannot be allocated the call runs single rounds.
+ * For fp32 matrices with n a multiple of 128 and 16-byte aligned rows,
+ * phase 2 of every round of 128 also writes its block column transposed, and
+ * the bulk of phase 3 reads it, in pairs or in single rounds (the operands
+ * then go straight from memory into LDS).  The copies take 8 x 128 x 128q x 4
+ * bytes (32 MiB at n = 8192, 64 MiB at n = 16384, 1 GiB at n = 262144),
+ * allocated with the helper streams on first need and grown for a larger n;
+ * growing synchronises `stream` and the helper streams inside the call
+ * (solves still running on them may read the old copies).  When they cannot
+ * be allocated the call runs single rounds without them.
  * Nothing else is allocated.
  * Solves enqueued on the same stream from several host threads are
  * serialised by the library.
