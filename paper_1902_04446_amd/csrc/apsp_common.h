@@ -57,9 +57,13 @@ struct OpF32 {
 };
 
 //  * OpI32F: int32 storage, fp32 arithmetic.  Values are converted as they
-//    are loaded (v >= 2^30 -> +inf, else (float)v) and back as they are
-//    stored (+inf -> 2^30).  Exact whenever every sum the method forms is an
-//    integer below 2^24.  Every value the blocked method stores is the length
+//    are loaded ((float)min(v, 2^30): "no edge" stays the finite 2^30) and
+//    back as they are stored (min(v, 2^30) of the integer value).  A sum with
+//    a "no edge" term is at least 2^30, above every path length (< 2^24), so
+//    it never wins a minimum against one and is stored as 2^30; stored
+//    values only decrease, so no sum exceeds 2^31 (exact in fp32).  Padding
+//    outside the matrix is +inf.  Exact whenever every sum of two path lengths
+//    the method forms is an integer below 2^24.  Every value the blocked method stores is the length
 //    of a shortest path over some subset of intermediate vertices, so at most
 //    (n-1) * wmax for the largest finite weight wmax, and every sum it forms
 //    adds two of them: 2 (n-1) wmax < 2^24 is sufficient (int_exact_in_f32).
@@ -79,10 +83,11 @@ struct OpI32F {
     }
     static __device__ __forceinline__ uint32_t pad() { return kInfF32Bits; }
     static __device__ __forceinline__ uint32_t norm(uint32_t v) {
-        return v >= kInfI32 ? kInfF32Bits : __float_as_uint((float)v);
+        return __float_as_uint((float)(v < kInfI32 ? v : kInfI32));
     }
     static __device__ __forceinline__ uint32_t out(uint32_t v) {
-        return v == kInfF32Bits ? kInfI32 : (uint32_t)__uint_as_float(v);
+        const uint32_t x = (uint32_t)__uint_as_float(v);
+        return x < kInfI32 ? x : kInfI32;
     }
 };
 
