@@ -47,12 +47,12 @@ __device__ __forceinline__ void batched_item(uint32_t *D, int n, int64_t ld, boo
     uint32_t acc[8][8];
     tile::load_acc<Op, true>(acc, D, ld, i0, j0, mr, nc, vec);
     if (CLOSE_ONLY) {
-        tile::close_block_pairs<Op>(acc, kw, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+        tile::close_block<Op>(acc, kw, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
     } else {
         // a tile whose valid rows / columns fit in 64 updates only those
         tile::minplus_tile<Op, true, true>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
         if (I == r + 1 && J == r + 1)  // phase 1 of round r+1, fused
-            tile::close_block_pairs<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+            tile::close_block<Op>(acc, mr, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
     }
     tile::store_acc<Op>(acc, D, ld, i0, j0, mr, nc, vec);
 }
@@ -68,11 +68,11 @@ __device__ __forceinline__ void batched_item64(uint32_t *D, int n, int64_t ld, b
     uint32_t acc[4][4];
     tile64::load64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
     if (CLOSE_ONLY) {
-        tile64::close64_pairs<Op>(acc, kw, L);
+        tile64::close64<Op>(acc, kw, L);
     } else {
         tile64::update64<Op>(acc, D, ld, i0, j0, kb, mr, nc, kw, vec, L);
         if (I == r + 1 && J == r + 1)  // phase 1 of round r+1, fused
-            tile64::close64_pairs<Op>(acc, mr, L);
+            tile64::close64<Op>(acc, mr, L);
     }
     tile64::store64<Op>(acc, D, ld, i0, j0, mr, nc, vec);
 }
@@ -91,11 +91,14 @@ __device__ __forceinline__ void any_item(const BatchDesc &g, bool vec, int I, in
 // One work item per workgroup: a tile of round r of one graph, at that
 // graph's round width (g.tile, 64 or 128).  DT 0: int32 graphs, each on the
 // fp32 pipe (OpI32F) when its largest finite weight wmax[graph] allows it
-// bit-exactly, else in uint32; DT 1: fp32.  Built for 3 workgroups per CU
-// (at most 168 VGPRs): the pivot-pair closure holds two published rows and
-// columns beside the 64 accumulators and would spill under a 128 cap.
+// bit-exactly, else in uint32; DT 1: fp32.  A closure-only launch (phase 1
+// of the first round) is bound by its serial pivot chains, so it is built
+// for 4 workgroups per CU rather than 3: more closures overlap per CU.  The
+// closures take one pivot per barrier here: measured on the 4096-graph
+// batch, the pivot-pair form (which needs 3 workgroups per CU to hold its
+// two published rows and columns without spilling) was 1.5-2 % slower.
 template <int DT, bool CLOSE_ONLY>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_batched(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CLOSE_ONLY ? 4 : 3))) void k_batched(
     const BatchDesc *__restrict__ descs, const BatchItem *__restrict__ items, XcdRanges ranges,
     int r, const uint32_t *__restrict__ wmax) {
     constexpr size_t kLds =

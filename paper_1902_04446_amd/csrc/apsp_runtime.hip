@@ -1,6 +1,8 @@
 // Round scheduler of the single-graph solver: enqueues the phases of the
 // blocked method (arXiv:1902.04446, Sec. 4.4/4.5, Algorithms 3 and 4) with a
-// one-round lookahead over two HIP streams.
+// one-round lookahead over the library's own streams of the caller's stream
+// (a chain stream S, which starts after the caller's earlier work and which
+// the caller's stream waits for at the end, and band streams H).
 //
 // The paper's rounds are strictly ordered: phase 1 of round r+1 needs the
 // diagonal block that phase 3 of round r produced.  Only the tiles in block
@@ -10,9 +12,10 @@
 //   A(r) = phase-3 tiles in block row/column r+1      (kNext, 2q-3 tiles)
 //   B(r) = every other phase-3 tile                     (kRest, (q-2)^2 tiles)
 //
-// and the caller's stream S runs the short critical chain
+// and the chain stream S runs the short critical chain
 //   P2(r) -> [wait B(r-1)] -> A(r) -> P2(r+1) -> [wait B(r)] -> A(r+1) -> ...
-// while a helper stream H runs B(r) as soon as P2(r) is done.  Phase 1 of
+// while a band stream H runs B(r) as soon as P2(r) is done.  (Below the
+// lookahead's round count everything runs on the caller's stream.)  Phase 1 of
 // round r+1 is fused into A(r): the workgroup that produces diagonal block
 // r+1 closes it in registers before storing it, so no single-workgroup
 // kernel has to find room on a GPU filled by B(r).  B(r) overlaps A(r) and
@@ -24,7 +27,7 @@
 //     and read the diagonal block r+1; none of these is touched by B(r);
 //   * A(r+1) rewrites row/column r+2 tiles, which B(r) wrote, so S waits
 //     for B(r) first.
-// B(r) itself runs as bands of block rows on separate helper streams; band g
+// B(r) itself runs as bands of block rows on separate band streams; band g
 // of round r+1 follows band g of round r on its stream and reads only the
 // panels of round r+1 and its own tiles, so it does not wait for the other
 // bands of B(r), except the band holding block row r: that row was the row

@@ -578,102 +578,5 @@ __device__ __forceinline__ void close_block(uint32_t (&acc)[8][8], int kw, uint3
     }
 }
 
-// close_block with one barrier per two pivots (the batched solver, whose
-// closure launches are bound by throughput rather than by one chain).  For
-// pivots k, k+1 (k even, so both are held by the same threads) the holders
-// publish rows and columns k and k+1 as they stand before pivot k; every
-// thread forms the entries pivot k gives column k+1 and row k+1 at its own
-// rows i and columns j,
-//     c'_i = min(d_i,k+1, d_ik + d_k,k+1)     r'_j = min(d_k+1,j, d_k+1,k + d_kj),
-// the sequential loop's operations on them (pivot k changes neither row nor
-// column k, d_kk being 0), and applies both pivots with one three-input
-// minimum, d_ij = min3(d_ij, d_ik + d_kj, c'_i + r'_j): the same two sums and
-// an exact minimum, so the bits of the sequential loop.  Fewer VALU
-// instructions per pivot than close_block (1.5 instead of 2 per entry) and
-// half its barriers.  `lds` needs 1024 words.
-template <class Op>
-__device__ __forceinline__ void close_block_pairs(uint32_t (&acc)[8][8], int kw, uint32_t *lds) {
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    const bool big = kw > 64;
-    auto read8 = [&](const uint32_t *v, int base, uint32_t (&out)[8]) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(&v[h * 64 + base]);
-            out[h * 4 + 0] = x.x;
-            out[h * 4 + 1] = x.y;
-            out[h * 4 + 2] = x.z;
-            out[h * 4 + 3] = x.w;
-        }
-    };
-    // pivots k = 64 kh + 4 kq + u: kh and u are unrolled so that the register
-    // row/column of a pivot (4 kh + u) is a compile-time index
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-        for (int kq = 0; kq < 16; ++kq) {
-#pragma unroll
-            for (int u = 0; u < 4; u += 2) {
-                const int k = kh * 64 + kq * 4 + u;
-                const int mk = kh * 4 + u;
-                if (k < kw) {  // uniform over the workgroup
-                    const bool pair = k + 1 < kw;
-                    uint32_t *b = lds + ((k >> 1) & 1) * 512;
-                    uint32_t *r0 = b, *r1 = b + 128, *c0 = b + 256, *c1 = b + 384;
-                    if (ty == kq) {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            *reinterpret_cast<uint4 *>(&r0[h * 64 + tx * 4]) =
-                                make_uint4(acc[mk][h * 4 + 0], acc[mk][h * 4 + 1],
-                                           acc[mk][h * 4 + 2], acc[mk][h * 4 + 3]);
-                            *reinterpret_cast<uint4 *>(&r1[h * 64 + tx * 4]) =
-                                make_uint4(acc[mk + 1][h * 4 + 0], acc[mk + 1][h * 4 + 1],
-                                           acc[mk + 1][h * 4 + 2], acc[mk + 1][h * 4 + 3]);
-                        }
-                    }
-                    if (tx == kq) {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            *reinterpret_cast<uint4 *>(&c0[h * 64 + ty * 4]) =
-                                make_uint4(acc[h * 4 + 0][mk], acc[h * 4 + 1][mk],
-                                           acc[h * 4 + 2][mk], acc[h * 4 + 3][mk]);
-                            *reinterpret_cast<uint4 *>(&c1[h * 64 + ty * 4]) =
-                                make_uint4(acc[h * 4 + 0][mk + 1], acc[h * 4 + 1][mk + 1],
-                                           acc[h * 4 + 2][mk + 1], acc[h * 4 + 3][mk + 1]);
-                        }
-                    }
-                    __syncthreads();
-                    uint32_t ck[8], ck1[8], rk[8], rk1[8];
-                    read8(c0, ty * 4, ck);
-                    read8(r0, tx * 4, rk);
-                    if (pair) {
-                        // pivot k applied to column and row k+1 (the loop's own operations)
-                        const uint32_t dk_k1 = r0[k + 1], dk1_k = r1[k];
-                        read8(c1, ty * 4, ck1);
-                        read8(r1, tx * 4, rk1);
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) ck1[m] = Op::min2(ck1[m], Op::add(ck[m], dk_k1));
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) rk1[e] = Op::min2(rk1[e], Op::add(dk1_k, rk[e]));
-#pragma unroll
-                        for (int m = 0; m < 8; ++m)
-#pragma unroll
-                            for (int e = 0; e < 8; ++e)
-                                if (big || (m < 4 && e < 4))
-                                    acc[m][e] = Op::min3(acc[m][e], Op::add(ck[m], rk[e]),
-                                                         Op::add(ck1[m], rk1[e]));
-                    } else {  // the last pivot of an odd kw
-#pragma unroll
-                        for (int m = 0; m < 8; ++m)
-#pragma unroll
-                            for (int e = 0; e < 8; ++e)
-                                if (big || (m < 4 && e < 4))
-                                    acc[m][e] = Op::min2(acc[m][e], Op::add(ck[m], rk[e]));
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();  // every read of the published rows done before the LDS is reused
-}
-
 }  // namespace tile
 }  // namespace apsp
