@@ -5,7 +5,7 @@ method in the launch configuration the benchmark times (apsp_solve_rounds,
 round width 128) and checks sampled rows of the state they leave against the
 host oracle: after rounds 0..R-1 the matrix is the Floyd-Warshall state after
 pivots 0..128R-1, whose rows the oracle builds from the adjacency lists.
-The whole solve (about 9 minutes) runs only when APSP_FULL_262144 is set.
+The whole solve (about 8 minutes) runs only when APSP_FULL_262144 is set.
 """
 import os
 import time
@@ -60,7 +60,7 @@ def test_stretch_262144_first_rounds(hubs):
 
 
 @pytest.mark.skipif(not os.environ.get("APSP_FULL_262144"),
-                    reason="a whole n = 262144 solve takes about 9 minutes; "
+                    reason="a whole n = 262144 solve takes about 8 minutes; "
                            "set APSP_FULL_262144=1 to run it")
 def test_stretch_262144_full_solve():
     """The whole n = 262144 Swiss-roll kNN solve (2048 rounds of width 128, in
