@@ -270,12 +270,17 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
     # kernels) and replayed: one submission for all of its launches
     reset()
     torch.cuda.synchronize()
-    hip_graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(hip_graph):
-        plan.run()
-    t_graph = timed(hip_graph.replay)
-    same = same and same_as(ref)
-    del hip_graph
+    t_graph = None
+    try:
+        hip_graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(hip_graph):
+            plan.run()
+    except RuntimeError as exc:  # reported, not fatal: the eager figures stand
+        log(f"batched: HIP graph capture failed: {exc}")
+    else:
+        t_graph = timed(hip_graph.replay)
+        same = same and same_as(ref)
+        del hip_graph
     t0 = time.perf_counter()
     args = apsp.BatchArgs(work)  # the list marshalled once (Python work, ~1 us per matrix)
     t_marshal = time.perf_counter() - t0
@@ -295,7 +300,7 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
         t_loop = timed(loop)
         same = same and same_as(ref)
     log(f"batched: tuned plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches), "
-        f"replayed from a HIP graph {t_graph * 1e3:.2f} ms; "
+        f"replayed from a HIP graph {t_graph * 1e3 if t_graph is not None else float('nan'):.2f} ms; "
         f"width 128 only {fixed[128][0] * 1e3:.2f} ms, width 64 only {fixed[64][0] * 1e3:.2f} ms; "
         f"one-shot call {t_oneshot * 1e3:.2f} ms, allocation-free call {t_noalloc * 1e3:.2f} ms "
         f"(marshalling the list {t_marshal * 1e3:.2f} ms), per-graph loop {t_loop * 1e3:.2f} ms, "
@@ -308,7 +313,7 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
             "autotune_s": round(t_tune, 3),
             "width128_only_ms": round(fixed[128][0] * 1e3, 3),
             "width64_only_ms": round(fixed[64][0] * 1e3, 3),
-            "graph_replay_ms": round(t_graph * 1e3, 3),
+            "graph_replay_ms": round(t_graph * 1e3, 3) if t_graph is not None else None,
             "oneshot_call_ms": round(t_oneshot * 1e3, 3),
             "noalloc_call_ms": round(t_noalloc * 1e3, 3),
             "python_marshal_ms": round(t_marshal * 1e3, 3),
