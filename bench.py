@@ -207,11 +207,14 @@ def cpu_baseline(n: int, u, v, w, target_s: float) -> dict:
             "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
 
 
-def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True) -> dict:
+def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True,
+                  profile_only: bool = False) -> dict:
     """Many small graphs: one batched launch vs a loop of single-graph solves.
 
     4096 ER graphs, n log-uniform in [32, 512], p = 8/n, int32 U{1..1000}.
-    The metric is sum(n_i^3) / t over the whole batch.
+    The metric is sum(n_i^3) / t over the whole batch.  ``profile_only``:
+    exactly one run of a width-128 plan (for a profiler to see one run's
+    launches), timed, nothing else.
     """
     import graphgen as gg
 
@@ -243,6 +246,20 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
 
     def same_as(ref):
         return all(torch.equal(a, b) for a, b in zip(ref, work))
+
+    if profile_only:
+        reset()
+        p_ = apsp.BatchPlan(work, tile=128)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_.run()
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        info = p_.info()
+        p_.close()
+        log(f"batched: one width-128 plan run {t_one * 1e3:.2f} ms ({info['launches']} launches)")
+        return {"workload": f"{count} ER graphs, n log-uniform [32,512], p=8/n, int32 U{{1..1000}}",
+                "profile_only": True, "one_run_ms": round(t_one * 1e3, 3), "plan": info}
 
     # fixed widths first, then the autotuned table (which plans created after
     # the tuning pick up)
@@ -745,6 +762,8 @@ def main() -> int:
                     help="CPU time budget of the oracle baseline sample (0 disables it)")
     ap.add_argument("--batched-loop", type=int, default=1,
                     help="also time the batch as a loop of single-graph solves (0 skips it)")
+    ap.add_argument("--batched-profile", type=int, default=0,
+                    help="1: the batched section is exactly one width-128 plan run (for profilers)")
     ap.add_argument("--long-run", type=int, default=1,
                     help="one full n=65536 solve with per-phase times (0 disables it)")
     ap.add_argument("--stretch-rounds", type=int, default=4,
@@ -824,7 +843,8 @@ def main() -> int:
     batched = None
     if args.batched > 0:
         batched = bench_batched(apsp, torch, dev, args.batched, reps=3,
-                                loop_too=bool(args.batched_loop))
+                                loop_too=bool(args.batched_loop),
+                                profile_only=bool(args.batched_profile))
 
     serving = None
     if args.serving > 0:
