@@ -21,6 +21,7 @@ __all__ = [
     "round_width", "batched_round_width", "num_rounds", "version",
     "TUNE_BUCKETS", "batched_tuning", "set_batched_tuning", "batched_autotune",
     "batched_autotune_batch", "set_round_pair_threshold", "set_width64_max_n",
+    "set_aligned_copy_min_n",
     "stream_state_bytes", "stream_state_count", "release_stream_state",
 ]
 
@@ -67,6 +68,7 @@ def _load() -> ctypes.CDLL:
         "apsp_batched_round_width": ([i64, i32], i32),
         "apsp_set_round_pair_threshold": ([i32], i32),
         "apsp_set_width64_max_n": ([i64], i64),
+        "apsp_set_aligned_copy_min_n": ([i64], i64),
         "apsp_stream_state_bytes": ([i64, i32], i64),
         "apsp_stream_state_count": ([], i64),
         "apsp_release_stream_state": ([vp], i32),
@@ -180,6 +182,17 @@ def set_width64_max_n(n: int) -> int:
     prev = int(_LIB.apsp_set_width64_max_n(int(n)))
     if prev < 0:
         raise ValueError("the limit is a vertex count in [0, 8192]")
+    return prev
+
+
+def set_aligned_copy_min_n(n: int) -> int:
+    """Smallest n from which a matrix whose rows are not 16-byte aligned is
+    solved in an aligned working copy (process-wide; default 512; a value
+    above every n turns the copy off); returns the previous value.  The
+    result is the same either way."""
+    prev = int(_LIB.apsp_set_aligned_copy_min_n(int(n)))
+    if prev < 0:
+        raise ValueError("the threshold is a vertex count >= 0")
     return prev
 
 

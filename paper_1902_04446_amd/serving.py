@@ -195,10 +195,17 @@ class GpuBackend:
         # drained, so that wait is already over).
         self._staging = [dict() for _ in range(slots)]
 
+    @staticmethod
+    def _ld(n: int) -> int:
+        # rows padded to 16 bytes: the library then solves every slice in
+        # place (rows off 16 bytes would be copied into an aligned working
+        # copy for each slice)
+        return (n + 3) // 4 * 4
+
     def bytes_needed(self, n: int, checkpoints: int = 0) -> int:
         """Device bytes a request holds while admitted: its matrix and its
-        checkpoint buffers."""
-        return 4 * n * n * (1 + checkpoints)
+        checkpoint buffers (rows padded to a multiple of 4 elements)."""
+        return 4 * n * self._ld(n) * (1 + checkpoints)
 
     def state_bytes(self, n: int) -> int:
         """Device bytes of the solver's state that a slot stream keeps once it
@@ -217,7 +224,7 @@ class GpuBackend:
         # on that stream precede this request's work
         tdt = self.torch.float32 if self.dtype == "f32" else self.torch.int32
         with self.torch.cuda.stream(self.streams[slot]):
-            return self.torch.empty((n, n), dtype=tdt, device=self.device)
+            return self.torch.empty((n, self._ld(n)), dtype=tdt, device=self.device)[:, :n]
 
     def alloc(self, req: Request, slot: int):
         return self._empty(req.n, slot)

@@ -195,6 +195,22 @@ def test_width64_limit_setter(lib):
         lib.apsp_set_width64_max_n(prev)
 
 
+def test_aligned_copy_threshold_setter(lib):
+    """No HIP call: the threshold of the aligned working copy is a
+    process-wide vertex count >= 0 (default 512)."""
+    prev = lib.apsp_set_aligned_copy_min_n(1000)
+    try:
+        assert prev >= 0
+        assert lib.apsp_set_aligned_copy_min_n(-1) == -1
+        assert lib.apsp_set_aligned_copy_min_n(1 << 40) == 1000
+        assert lib.apsp_set_aligned_copy_min_n(0) == 1 << 40
+    finally:
+        lib.apsp_set_aligned_copy_min_n(prev)
+    # n == 0 with an ld off 4 is still a no-op that touches no device
+    assert lib.apsp_solve(None, 0, 3, 0, None) == 0
+    assert lib.apsp_solve_rounds(None, 0, 3, 1, 0, 5, None) == 0
+
+
 def test_round_pair_threshold_setter(lib):
     """No HIP call: the setter swaps a process-wide value and rejects < 2."""
     prev = lib.apsp_set_round_pair_threshold(9)

@@ -1136,3 +1136,77 @@ def test_fp32_nonzero_diagonal(apsp, dev, n):
     assert np.array_equal(views[2].cpu().numpy(), ref128), "batched width 128"
     for p in plans:
         p.close()
+
+
+# ------------------------------------------- rows that are not 16-byte aligned
+
+@pytest.fixture
+def aligned_copy_threshold(apsp):
+    prev = apsp.set_aligned_copy_min_n(256)
+    yield apsp
+    apsp.set_aligned_copy_min_n(prev)
+
+
+def _solve_with_copy(apsp, W, dev, copy, fn=None, **kw):
+    import torch
+
+    prev = apsp.set_aligned_copy_min_n(256 if copy else 1 << 40)
+    try:
+        view, buf = _to_dev(W, dev, **kw)
+        (fn or apsp.solve)(view)
+        torch.cuda.synchronize()
+        return view.cpu().numpy(), buf
+    finally:
+        apsp.set_aligned_copy_min_n(prev)
+
+
+@pytest.mark.parametrize("n,dtype", [(300, np.int32), (1001, np.float32), (2047, np.int32),
+                                     (6001, np.float32), (9219, np.float32)])
+def test_aligned_working_copy(aligned_copy_threshold, dev, n, dtype):
+    """A matrix whose rows are off 16 bytes (ld = n with n % 4 != 0, or a base
+    4 bytes off) is solved in an aligned working copy: the result equals the
+    in-place solve on the word-by-word path bit for bit, the padding around
+    the matrix is untouched, and (small n) the result equals the oracle.
+    9219 vertices take round pairs, 6001 single rounds of 128, 2047 and below
+    rounds of 64."""
+    import torch
+
+    apsp = aligned_copy_threshold
+    W = _er(n, 8.0 / n, 9800 + n)[0] if dtype == np.int32 else _swiss(n, 9800 + n)[0]
+    ref, _ = _solve_with_copy(apsp, W, dev, copy=False)
+    got, buf = _solve_with_copy(apsp, W, dev, copy=True)
+    assert np.array_equal(got, ref)
+    # base 4 bytes off 16, leading dimension a multiple of 4
+    got_off, buf_off = _solve_with_copy(apsp, W, dev, copy=True, ld=n + (4 - n % 4) % 4 + 4,
+                                        offset=1)
+    assert np.array_equal(got_off, ref)
+    ld = n + (4 - n % 4) % 4 + 4
+    pad = buf_off[1:1 + n * ld].view(n, ld)[:, n:]
+    assert (pad.cpu().numpy() == (-7 if dtype == np.int32 else -3.5)).all()
+    if n <= 1001:
+        exp = oracle.fw(W) if dtype == np.int32 else oracle.blocked(W, apsp.round_width(n))
+        assert np.array_equal(got, exp)
+    # round slices, each call through its own working copy
+    q = apsp.num_rounds(n)
+    view, _ = _to_dev(W, dev)
+    cuts = [0, 1, q // 3, q]
+    for r0, r1 in zip(cuts[:-1], cuts[1:]):
+        apsp.solve_rounds(view, r0, r1)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy(), ref), "round slices"
+    # profiled: synchronous, the same bits
+    view, _ = _to_dev(W, dev)
+    apsp.solve_profiled(view)
+    assert np.array_equal(view.cpu().numpy(), ref), "profiled"
+
+
+@pytest.mark.parametrize("n", [301, 1001])
+def test_aligned_working_copy_symmetric(aligned_copy_threshold, dev, n):
+    """The symmetric solver on rows off 16 bytes, through the working copy
+    (junk in the lower triangle, which it overwrites), against the oracle."""
+    apsp = aligned_copy_threshold
+    W = _swiss(n, 9900 + n)[0]
+    junk = W.copy()
+    junk[np.tril_indices(n, -1)] = np.float32(7.0)
+    got, _ = _solve_with_copy(apsp, junk, dev, copy=True, fn=apsp.solve_symmetric)
+    assert np.array_equal(got, oracle.blocked(W, 128))
