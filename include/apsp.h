@@ -99,14 +99,19 @@ enum {
  * growing synchronises `stream` and the helper streams inside the call
  * (solves still running on them may read the old copies).  When they cannot
  * be allocated the call runs single rounds without them.
- * Rows that are not 16-byte aligned (ld not a multiple of 4, or dist not on
- * 16 bytes) would take the kernels' word-by-word load path, about 1.45x
- * slower.  From n = 512 (apsp_set_aligned_copy_min_n) such a matrix is
- * copied into an aligned working copy of n x (n rounded up to 4) words
- * (hipMallocAsync on `stream`), solved there and copied back, in stream
- * order, and the copy is freed with hipFreeAsync behind that work; when it
- * cannot be allocated the solve runs in place.  The result is the same,
- * bit for bit, either way.
+ * Working copy.  Rows that are not 16-byte aligned (ld not a multiple of 4,
+ * or dist not on 16 bytes) would take the kernels' word-by-word load path,
+ * about 1.45x slower; rounds of 128 with n not a multiple of 128 run 6-7 %
+ * slower than the same matrix padded to a multiple of 128.  From n = 512
+ * (apsp_set_aligned_copy_min_n) such a call runs on a working copy: rows
+ * padded to 4 elements and, for a matrix of 64 or more rounds of 128
+ * (n > 8064) and a call of 16 or more rounds, n padded to a multiple of 128
+ * with vertices that have no edges (which changes no operation on the real
+ * entries).  The copy (at most n' x n' words, n' the
+ * padded n) comes from hipMallocAsync on `stream`, is filled, solved and
+ * copied back in stream order, and is freed with hipFreeAsync behind that
+ * work; when it cannot be allocated the call runs in place.  The result is
+ * the same, bit for bit, either way.
  * Nothing else is allocated.
  * Solves enqueued on the same stream from several host threads are
  * serialised by the library.
@@ -215,9 +220,9 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
  * `stream`, as in apsp_solve.  From 2 rounds on the call uses the per-stream
  * state of apsp_solve (helper streams, and the panel copies, of which it
  * uses two slots: 256 + 8 x 128 x 128q x 4 bytes, allocated or grown as
- * described there).  Rows that are not 16-byte aligned are handled as in
- * apsp_solve (an aligned working copy from n = 512, the whole matrix copied
- * in and back).  Asynchronous.  Returns as apsp_solve, or
+ * described there).  Layouts that would be slow get the working copy of
+ * apsp_solve (from n = 512; the whole matrix copied in and back).
+ * Asynchronous.  Returns as apsp_solve, or
  * APSP_ERR_NO_MEMORY when the copies cannot be allocated.
  */
 int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream);
@@ -244,10 +249,10 @@ int64_t apsp_set_width64_max_n(int64_t n);
 
 /* apsp_set_aligned_copy_min_n -- the smallest n from which apsp_solve,
  * apsp_solve_rounds (each call), apsp_solve_profiled and apsp_solve_symmetric
- * solve a matrix whose rows are not 16-byte aligned in an aligned working
- * copy (see apsp_solve; default 512; a value above every n turns the copy
- * off).  Process-wide, for calls made afterwards; no HIP call.  Returns the
- * previous value, or -1 (unchanged) when n < 0. */
+ * run on a working copy (see apsp_solve: rows not 16-byte aligned, or n not
+ * a multiple of 128 with rounds of 128; default 512; a value above every n
+ * turns the copy off).  Process-wide, for calls made afterwards; no HIP call.
+ * Returns the previous value, or -1 (unchanged) when n < 0. */
 int64_t apsp_set_aligned_copy_min_n(int64_t n);
 
 /*

@@ -186,10 +186,11 @@ def set_width64_max_n(n: int) -> int:
 
 
 def set_aligned_copy_min_n(n: int) -> int:
-    """Smallest n from which a matrix whose rows are not 16-byte aligned is
-    solved in an aligned working copy (process-wide; default 512; a value
-    above every n turns the copy off); returns the previous value.  The
-    result is the same either way."""
+    """Smallest n from which a solve whose layout would be slow (rows not
+    16-byte aligned, or n not a multiple of 128 with rounds of 128) runs on
+    a working copy (process-wide; default 512; a value above every n turns
+    the copy off); returns the previous value.  The result is the same either
+    way."""
     prev = int(_LIB.apsp_set_aligned_copy_min_n(int(n)))
     if prev < 0:
         raise ValueError("the threshold is a vertex count >= 0")

@@ -41,46 +41,76 @@ int32_t check_matrix(const void *dist, int64_t n, int64_t ld, int32_t dtype) {
     return APSP_OK;
 }
 
-// A matrix whose rows are not 16-byte aligned (ld % 4 != 0, or a base
-// address off 16 bytes) takes the kernels' word-by-word load path, which
-// measured about 1.45x slower (n = 8191: 24.3 against 16.7 ms; n = 16461:
-// 177.5 against 124.2 ms).  From this many vertices such a matrix is solved
-// in an aligned working copy (ld rounded up to 4, stream-ordered allocation,
-// copied in and back on the caller's stream: about 0.1 ms each way at
-// n = 8192); when that copy cannot be allocated the solve runs in place.
-// Measured with the copy against in place: n = 255 0.150 / 0.145 ms, 511
-// 0.259 / 0.274, 2047 1.10 / 1.29, 8191 17.2 / 24.3, 16461 125.3 / 177.6.
+// Working copy.  Two layouts make a solve slower than it needs to be:
+//  * rows that are not 16-byte aligned (ld % 4 != 0, or a base address off
+//    16 bytes) take the kernels' word-by-word load path: about 1.45x slower
+//    (n = 8191: 24.3 against 16.7 ms; n = 16461: 177.5 against 124.2 ms);
+//  * with rounds of 128 and n not a multiple of 128 the tiles of the last
+//    block row and column are partial, and the operands cannot be staged
+//    straight into LDS anywhere: 6-7 % slower than the same matrix padded to
+//    a multiple of 128 with isolated vertices (n = 8300: 18.3 against
+//    17.0 ms; n = 16461: 124.4 against 115.8 ms).  Below 64 rounds the
+//    padding and the copies cost what the staging gains (n = 5200: 6.11
+//    against 6.09 ms; n = 6000: 7.80 against 7.77 ms), so only matrices of 64
+//    or more rounds are padded.
+// From g_aligned_copy_min_n vertices such a call runs on a working copy: rows
+// padded to 4 elements, and, for the second case, n padded to a multiple of
+// 128 with vertices that have no edges (+inf, or 2^30, off the diagonal; 0 on
+// it).  A vertex with no edges is no intermediate vertex of any path and its
+// own entries stay "no edge" through every round, and the real vertices keep
+// their blocks, so the rounds perform exactly the same operations on the real
+// entries: the result is the same bits.  The copy is stream-ordered
+// (hipMallocAsync on the caller's stream), filled and copied back by row-copy
+// kernels (about 0.1 ms each way at n = 8192) and freed behind that work; a
+// call of fewer than 16 rounds is not padded (the copies would cost more than
+// the rounds gain), and without memory for the copy the call runs in place.
+// Measured with the copy against in place, contiguous (unaligned) rows: n =
+// 255 0.150 / 0.145 ms, 511 0.259 / 0.274, 2047 1.10 / 1.29, 8191 16.97 /
+// 24.41, 16461 119.4 / 179.1; rows padded to 4 (padding to 128 only): 8300
+// 17.70 / 18.45, 12000 47.40 / 50.11, 16461 119.2 / 126.9.
 constexpr int64_t kDefaultAlignedCopyMinN = 512;
+constexpr int64_t kPadMinRounds = 16;     // rounds in the call
+constexpr int64_t kPadMinMatrixRounds = 64;  // rounds of the whole matrix
 std::atomic<int64_t> g_aligned_copy_min_n{kDefaultAlignedCopyMinN};
 
-bool wants_aligned_copy(const void *dist, int64_t n, int64_t ld) {
+// The vertex count of the working copy of a call of `rounds` rounds on this
+// matrix, or 0 when the call runs in place.
+int64_t working_n(const void *dist, int64_t n, int64_t ld, int64_t rounds) {
+    if (n <= 0 || n < g_aligned_copy_min_n.load()) return 0;
     const bool aligned = (reinterpret_cast<uintptr_t>(dist) & 15u) == 0 && (ld & 3) == 0;
-    return n > 0 && !aligned && n >= g_aligned_copy_min_n.load();
+    const int64_t b = apsp::round_width(n);
+    const bool pad = b == apsp::kRoundB && n % b != 0 && rounds >= kPadMinRounds &&
+                     (n + b - 1) / b >= kPadMinMatrixRounds;
+    if (aligned && !pad) return 0;
+    return pad ? (n + b - 1) / b * b : n;
 }
 
-// Run solve(ptr, ld) on the matrix itself or on an aligned working copy of
-// it (see above); the copy's result is copied back only when solve succeeds.
+// Run solve(ptr, n, ld) on the matrix itself or on its working copy (see
+// above); the copy's result is copied back only when solve succeeds.
 template <class F>
-int32_t on_aligned_rows(void *dist, int64_t n, int64_t ld, hipStream_t s, F &&solve) {
-    if (!wants_aligned_copy(dist, n, ld)) return solve(static_cast<uint32_t *>(dist), ld);
-    const int64_t ldw = (n + 3) & ~(int64_t)3;
+int32_t on_working_copy(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t rounds,
+                        hipStream_t s, F &&solve) {
+    const int64_t nw = working_n(dist, n, ld, rounds);
+    if (nw == 0) return solve(static_cast<uint32_t *>(dist), n, ld);
+    const int64_t ldw = (nw + 3) & ~(int64_t)3;
     uint32_t *w = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void **>(&w), (size_t)n * (size_t)ldw * sizeof(uint32_t),
+    if (hipMallocAsync(reinterpret_cast<void **>(&w), (size_t)nw * (size_t)ldw * sizeof(uint32_t),
                        s) != hipSuccess) {
         (void)hipGetLastError();  // no room for the copy: solve in place
-        return solve(static_cast<uint32_t *>(dist), ld);
+        return solve(static_cast<uint32_t *>(dist), n, ld);
     }
     uint32_t *d = static_cast<uint32_t *>(dist);
-    hipError_t e = apsp::launch_copy_rows(w, ldw, d, ld, n, s);
+    const uint32_t none = dtype == APSP_I32 ? (uint32_t)APSP_INF_I32 : 0x7f800000u;
+    hipError_t e = apsp::launch_copy_pad(w, ldw, nw, d, ld, n, none, s);
     int32_t st = APSP_ERR_DEVICE;
     if (e != hipSuccess) {
-        apsp::note_error("aligned working copy", e);
+        apsp::note_error("working copy", e);
     } else {
-        st = solve(w, ldw);
+        st = solve(w, nw, ldw);
         if (st == APSP_OK) {
             e = apsp::launch_copy_rows(d, ld, w, ldw, n, s);
             if (e != hipSuccess) {
-                apsp::note_error("copy back from the aligned working copy", e);
+                apsp::note_error("copy back from the working copy", e);
                 st = APSP_ERR_DEVICE;
             }
         }
@@ -89,11 +119,20 @@ int32_t on_aligned_rows(void *dist, int64_t n, int64_t ld, hipStream_t s, F &&so
     return st;
 }
 
+// Rounds r0 .. r1-1 clamped to the matrix's q.
+int64_t call_rounds(int64_t n, int64_t r0, int64_t r1) {
+    const int64_t b = apsp::round_width(n);
+    const int64_t q = (n + b - 1) / b;
+    const int64_t hi = r1 < q ? r1 : q;
+    return hi > r0 ? hi - r0 : 0;
+}
+
 int32_t rounds_impl(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0, int64_t r1,
                     void *stream, apsp::PhaseTimes *times) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return on_aligned_rows(dist, n, ld, s, [&](uint32_t *D, int64_t ldD) -> int32_t {
-        const hipError_t e = apsp::run_rounds(D, n, ldD, dtype, r0, r1, r0 == 0, s, times);
+    return on_working_copy(dist, n, ld, dtype, call_rounds(n, r0, r1), s,
+                           [&](uint32_t *D, int64_t nD, int64_t ldD) -> int32_t {
+        const hipError_t e = apsp::run_rounds(D, nD, ldD, dtype, r0, r1, r0 == 0, s, times);
         if (e == hipErrorOutOfMemory) return APSP_ERR_NO_MEMORY;
         return e == hipSuccess ? APSP_OK : APSP_ERR_DEVICE;
     });
@@ -125,7 +164,7 @@ int32_t apsp_solve_profiled(void *dist, int64_t n, int64_t ld, int32_t dtype, vo
     apsp::PhaseTimes t;
     int32_t res = rounds_impl(dist, n, ld, dtype, 0, INT64_MAX, stream, &t);
     // synchronous, also when the result comes back from an aligned working copy
-    if (res == APSP_OK && wants_aligned_copy(dist, n, ld)) {
+    if (res == APSP_OK && working_n(dist, n, ld, call_rounds(n, 0, INT64_MAX)) != 0) {
         const hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
         if (e != hipSuccess) {
             apsp::note_error("hipStreamSynchronize", e);
@@ -249,8 +288,9 @@ int32_t apsp_solve_symmetric(void *dist, int64_t n, int64_t ld, int32_t dtype, v
     if (n == 0) return APSP_OK;
     if ((n + apsp::kRoundB - 1) / apsp::kRoundB > 46000) return APSP_ERR_INVALID_VALUE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return on_aligned_rows(dist, n, ld, s, [&](uint32_t *D, int64_t ldD) -> int32_t {
-        const hipError_t e = apsp::run_symmetric(D, n, ldD, dtype, s);
+    return on_working_copy(dist, n, ld, dtype, (n + apsp::kRoundB - 1) / apsp::kRoundB, s,
+                           [&](uint32_t *D, int64_t nD, int64_t ldD) -> int32_t {
+        const hipError_t e = apsp::run_symmetric(D, nD, ldD, dtype, s);
         if (e == hipErrorOutOfMemory) return APSP_ERR_NO_MEMORY;
         return e == hipSuccess ? APSP_OK : APSP_ERR_DEVICE;
     });

@@ -133,8 +133,12 @@ constexpr int kRest = 3;    // phase 3, tiles outside block rows/columns r, r+1,
 // ---- launchers (host side; each returns a hipError_t) ----------------------
 hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStream_t s);
 // dst[i * ldd + j] = src[i * lds + j] for i, j < n (the matrices must not overlap).
+// launch_copy_pad: the same for an nd x nd dst (nd >= n), whose vertices n ..
+// nd-1 get no edges (`none` off the diagonal, 0 on it).
 hipError_t launch_copy_rows(uint32_t *dst, int64_t ldd, const uint32_t *src, int64_t lds, int64_t n,
                             hipStream_t s);
+hipError_t launch_copy_pad(uint32_t *dst, int64_t ldd, int64_t nd, const uint32_t *src,
+                           int64_t lds, int64_t n, uint32_t none, hipStream_t s);
 hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s);
 // close_next_diag (kNext only): the workgroup of diagonal block r+1 also runs
 // phase 1 of round r+1 on it before storing it.

@@ -1210,3 +1210,34 @@ def test_aligned_working_copy_symmetric(aligned_copy_threshold, dev, n):
     junk[np.tril_indices(n, -1)] = np.float32(7.0)
     got, _ = _solve_with_copy(apsp, junk, dev, copy=True, fn=apsp.solve_symmetric)
     assert np.array_equal(got, oracle.blocked(W, 128))
+
+
+@pytest.mark.parametrize("n,dtype", [(8200, np.float32), (8300, np.int32), (9300, np.float32)])
+def test_padded_working_copy(aligned_copy_threshold, dev, n, dtype):
+    """Rounds of 128 with n not a multiple of 128 (64 or more rounds), rows
+    aligned: a call of 16 or more rounds runs on a copy padded to a multiple
+    of 128 with vertices that have no edges; the result equals the in-place
+    solve bit for bit and the caller's padding columns are untouched.  Round
+    slices mix padded calls (>= 16 rounds) and in-place ones.  8200 runs
+    single rounds of 128, 9300 round pairs, 8300 (int32) the fp32 pipe."""
+    import torch
+
+    apsp = aligned_copy_threshold
+    ld = n + (4 - n % 4) % 4 + 4
+    W = _er(n, 8.0 / n, 9850 + n)[0] if dtype == np.int32 else _swiss(n, 9850 + n)[0]
+    ref, _ = _solve_with_copy(apsp, W, dev, copy=False, ld=ld)
+    got, buf = _solve_with_copy(apsp, W, dev, copy=True, ld=ld)
+    assert np.array_equal(got, ref)
+    pad = buf[:n * ld].view(n, ld)[:, n:]
+    assert (pad.cpu().numpy() == (-7 if dtype == np.int32 else -3.5)).all()
+    q = apsp.num_rounds(n)
+    view, _ = _to_dev(W, dev, ld=ld)
+    cuts = [0, 20, 27, q]  # 20 rounds padded, 7 in place, the rest padded
+    for r0, r1 in zip(cuts[:-1], cuts[1:]):
+        apsp.solve_rounds(view, r0, r1)
+    torch.cuda.synchronize()
+    assert np.array_equal(view.cpu().numpy(), ref), "round slices"
+    if dtype == np.float32 and n == 8200:
+        sym, _ = _solve_with_copy(apsp, W, dev, copy=True, fn=apsp.solve_symmetric, ld=ld)
+        sym_ref, _ = _solve_with_copy(apsp, W, dev, copy=False, fn=apsp.solve_symmetric, ld=ld)
+        assert np.array_equal(sym, sym_ref), "symmetric"
