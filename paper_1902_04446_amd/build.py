@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["apsp_plain.hip", "apsp_pair.hip", "apsp_small.hip", "apsp_runtime.hip", "apsp_batched.hip",
            "apsp_batch_plan.hip", "apsp_autotune.hip", "apsp_minplus.hip", "apsp_symmetric.hip",
-           "apsp_api.hip"]
+           "apsp_copy.hip", "apsp_api.hip"]
 LIB = os.path.join(HERE, "libapsp.so")
 # diagnostic: VALU issue-rate probe used by the benchmark to state its ceiling
 PROBE_SOURCES = ["valu_probe.hip"]

@@ -53,49 +53,6 @@ __global__ __launch_bounds__(256) void k_diag_zero(uint32_t *__restrict__ D, int
     if (i < n) D[i * ld + i] = 0u;
 }
 
-// Copy the n x n words of src (leading dimension lds) to dst (ldd): the
-// aligned working copy of a matrix whose rows are not 16-byte aligned.  One
-// workgroup per row at a time; each thread moves four words of the row per
-// step, all four loaded before any is stored.
-__global__ __launch_bounds__(256) void k_copy_rows(uint32_t *__restrict__ dst, int64_t ldd,
-                                                   const uint32_t *__restrict__ src, int64_t lds,
-                                                   int64_t n) {
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint32_t *srow = src + i * lds;
-        uint32_t *drow = dst + i * ldd;
-        for (int64_t c = threadIdx.x; c < n; c += 1024) {
-            uint32_t v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = c + 256 * u < n ? srow[c + 256 * u] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (c + 256 * u < n) drow[c + 256 * u] = v[u];
-        }
-    }
-}
-
-// The nd x nd working copy of an n x n matrix (nd >= n): the matrix, then
-// vertices n .. nd-1 with no edges (`none` off the diagonal, 0 on it).
-__global__ __launch_bounds__(256) void k_copy_pad(uint32_t *__restrict__ dst, int64_t ldd,
-                                                  int64_t nd, const uint32_t *__restrict__ src,
-                                                  int64_t lds, int64_t n, uint32_t none) {
-    for (int64_t i = blockIdx.x; i < nd; i += gridDim.x) {
-        const uint32_t *srow = src + (i < n ? i : 0) * lds;  // read only for i < n
-        uint32_t *drow = dst + i * ldd;
-        for (int64_t c = threadIdx.x; c < nd; c += 1024) {
-            uint32_t v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t j = c + 256 * u;
-                v[u] = (i < n && j < n) ? srow[j] : (i == j ? 0u : none);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (c + 256 * u < nd) drow[c + 256 * u] = v[u];
-        }
-    }
-}
-
 // Domain check: int32 must be >= 0; fp32 must be >= 0 or -0 and not NaN.
 __global__ __launch_bounds__(256) void k_validate(const uint32_t *__restrict__ D, int64_t n,
                                                   int64_t ld, int is_f32,
@@ -314,22 +271,6 @@ hipError_t launch_prologue(uint32_t *D, int64_t n, int64_t ld, int dtype, hipStr
         hipLaunchKernelGGL(k_diag_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, n,
                            ld);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_pad(uint32_t *dst, int64_t ldd, int64_t nd, const uint32_t *src,
-                           int64_t lds, int64_t n, uint32_t none, hipStream_t s) {
-    if (nd <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)(nd < 8192 ? nd : 8192);
-    hipLaunchKernelGGL(k_copy_pad, dim3(grid), dim3(256), 0, s, dst, ldd, nd, src, lds, n, none);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_rows(uint32_t *dst, int64_t ldd, const uint32_t *src, int64_t lds, int64_t n,
-                            hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)(n < 8192 ? n : 8192);
-    hipLaunchKernelGGL(k_copy_rows, dim3(grid), dim3(256), 0, s, dst, ldd, src, lds, n);
     return hipGetLastError();
 }
 
