@@ -298,6 +298,26 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
         t_graph = timed(hip_graph.replay)
         same = same and same_as(ref)
         del hip_graph
+    # the same graphs in contiguous n x n buffers (rows off 16 bytes when n %
+    # 4 != 0): the plan gives those graphs working copies
+    contig = [torch.empty_like(p_) for p_ in pristine]
+
+    def reset_contig():
+        for c_, p_ in zip(contig, pristine):
+            c_.copy_(p_)
+
+    plan_c = apsp.BatchPlan(contig)
+    t_contig = float("inf")
+    for _ in range(reps):
+        reset_contig()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan_c.run()
+        torch.cuda.synchronize()
+        t_contig = min(t_contig, time.perf_counter() - t0)
+    plan_c.close()
+    same = same and all(torch.equal(a, b) for a, b in zip(ref, contig))
+    del contig
     t0 = time.perf_counter()
     args = apsp.BatchArgs(work)  # the list marshalled once (Python work, ~1 us per matrix)
     t_marshal = time.perf_counter() - t0
@@ -317,7 +337,8 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
         t_loop = timed(loop)
         same = same and same_as(ref)
     log(f"batched: tuned plan run {t_batched * 1e3:.2f} ms ({info['launches']} launches), "
-        f"replayed from a HIP graph {t_graph * 1e3 if t_graph is not None else float('nan'):.2f} ms; "
+        f"replayed from a HIP graph {t_graph * 1e3 if t_graph is not None else float('nan'):.2f} ms, "
+        f"on contiguous rows (working copies) {t_contig * 1e3:.2f} ms; "
         f"width 128 only {fixed[128][0] * 1e3:.2f} ms, width 64 only {fixed[64][0] * 1e3:.2f} ms; "
         f"one-shot call {t_oneshot * 1e3:.2f} ms, allocation-free call {t_noalloc * 1e3:.2f} ms "
         f"(marshalling the list {t_marshal * 1e3:.2f} ms), per-graph loop {t_loop * 1e3:.2f} ms, "
@@ -331,6 +352,7 @@ def bench_batched(apsp, torch, dev, count: int, reps: int, loop_too: bool = True
             "width128_only_ms": round(fixed[128][0] * 1e3, 3),
             "width64_only_ms": round(fixed[64][0] * 1e3, 3),
             "graph_replay_ms": round(t_graph * 1e3, 3) if t_graph is not None else None,
+            "contiguous_rows_ms": round(t_contig * 1e3, 3),
             "oneshot_call_ms": round(t_oneshot * 1e3, 3),
             "noalloc_call_ms": round(t_noalloc * 1e3, 3),
             "python_marshal_ms": round(t_marshal * 1e3, 3),

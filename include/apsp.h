@@ -251,8 +251,10 @@ int64_t apsp_set_width64_max_n(int64_t n);
  * apsp_solve_rounds (each call), apsp_solve_profiled and apsp_solve_symmetric
  * run on a working copy (see apsp_solve: rows not 16-byte aligned, or n not
  * a multiple of 128 with rounds of 128; default 512; a value above every n
- * turns the copy off).  Process-wide, for calls made afterwards; no HIP call.
- * Returns the previous value, or -1 (unchanged) when n < 0. */
+ * turns the copy off).  A value above APSP_BATCHED_MAX_N also turns off the
+ * batched working copies (see the batched plans).  Process-wide, for calls
+ * made afterwards (and plans created afterwards); no HIP call.  Returns the
+ * previous value, or -1 (unchanged) when n < 0. */
 int64_t apsp_set_aligned_copy_min_n(int64_t n);
 
 /*
@@ -324,6 +326,18 @@ int32_t apsp_solve_batched_noalloc(void *const *ptrs, const int32_t *ns, const i
  * frees the tables (hipFree, which waits for the device); the caller must
  * not destroy a plan whose runs are still pending on another stream.
  * apsp_batched_plan_info writes {launches, work items, tile updates}.
+ * Working copies: a graph whose rows are not 16-byte aligned (ld not a
+ * multiple of 4, or a pointer off 16 bytes) would take the kernels'
+ * word-by-word load path (the 4096-graph batch of n <= 512: 4.77 ms with
+ * contiguous rows in place, 4.49 ms on working copies, 3.76 ms with rows
+ * rounded up to 4 by the caller).  Plans and
+ * the one-shot calls give each such graph a working copy of n x (n rounded
+ * up to 4) words (plans: hipMalloc at creation, freed with the plan;
+ * one-shot calls: hipMallocAsync, freed stream-ordered), which every run
+ * fills first and copies back last; the results are the same bits.  The
+ * copies are off when apsp_set_aligned_copy_min_n is above
+ * APSP_BATCHED_MAX_N, and skipped when they cannot be allocated;
+ * apsp_solve_batched_noalloc makes none.
  * The plan keeps the matrix pointers, not the matrices: the caller keeps
  * them allocated while the plan is used.
  */

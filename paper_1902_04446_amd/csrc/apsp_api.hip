@@ -140,6 +140,8 @@ int32_t rounds_impl(void *dist, int64_t n, int64_t ld, int32_t dtype, int64_t r0
 
 }  // namespace
 
+int64_t apsp::aligned_copy_min_n() { return g_aligned_copy_min_n.load(); }
+
 extern "C" {
 
 int32_t apsp_solve(void *dist, int64_t n, int64_t ld, int32_t dtype, void *stream) {

@@ -139,6 +139,22 @@ hipError_t launch_copy_rows(uint32_t *dst, int64_t ldd, const uint32_t *src, int
                             hipStream_t s);
 hipError_t launch_copy_pad(uint32_t *dst, int64_t ldd, int64_t nd, const uint32_t *src,
                            int64_t lds, int64_t n, uint32_t none, hipStream_t s);
+// A batched graph's working copy: `user` (leading dimension ld_user) and
+// `work` (ld_work, 16-byte rows); its rows are rows row0 .. row0+n-1 of the
+// copy launch.
+struct BatchCopy {
+    uint32_t *user;
+    uint32_t *work;
+    int64_t ld_user, ld_work;
+    int64_t row0;
+    int32_t n, pad_;
+};
+// Copy every listed graph into its working copy (back == false) or back
+// (back == true); `rows` is the sum of their n.  Entries in row0 order.
+hipError_t launch_batch_copies(const BatchCopy *copies, int32_t count, int64_t rows, bool back,
+                               hipStream_t s);
+// Threshold of the working copies (apsp_set_aligned_copy_min_n).
+int64_t aligned_copy_min_n();
 hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s);
 // close_next_diag (kNext only): the workgroup of diagonal block r+1 also runs
 // phase 1 of round r+1 on it before storing it.

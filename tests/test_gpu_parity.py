@@ -1241,3 +1241,61 @@ def test_padded_working_copy(aligned_copy_threshold, dev, n, dtype):
         sym, _ = _solve_with_copy(apsp, W, dev, copy=True, fn=apsp.solve_symmetric, ld=ld)
         sym_ref, _ = _solve_with_copy(apsp, W, dev, copy=False, fn=apsp.solve_symmetric, ld=ld)
         assert np.array_equal(sym, sym_ref), "symmetric"
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.float32])
+def test_batched_working_copies(aligned_copy_threshold, dev, dtype):
+    """Batched graphs whose rows are off 16 bytes (ld = n with n % 4 != 0, a
+    base 4 bytes off) run on working copies: plan runs (twice), the one-shot
+    call and the allocation-free call (which runs them in place) all equal the
+    in-place plan bit for bit, and the int32 results equal the oracle."""
+    import torch
+
+    apsp = aligned_copy_threshold
+    sizes = [40, 63, 130, 257, 301, 513, 64, 200]
+    if dtype == np.int32:
+        Ws = [_directed_int(n, 9950 + n) for n in sizes]
+    else:
+        Ws = [_swiss(n, 9950 + n)[0] for n in sizes]
+
+    def fresh():
+        out = []
+        for k, W in enumerate(Ws):
+            offset = 1 if k == 3 else 0
+            ld = W.shape[0] + (4 if k == 3 else 0)
+            out.append(_to_dev(W, dev, ld=ld, offset=offset)[0])
+        return out
+
+    prev = apsp.set_aligned_copy_min_n(1 << 40)  # copies off: everything in place
+    try:
+        ref = fresh()
+        p = apsp.BatchPlan(ref)
+        p.run()
+        torch.cuda.synchronize()
+        p.close()
+    finally:
+        apsp.set_aligned_copy_min_n(prev)
+    ref = [r.cpu().numpy() for r in ref]
+    if dtype == np.int32:
+        for W, r in zip(Ws, ref):
+            assert np.array_equal(r.astype(np.int64), oracle.fw(W)), W.shape
+    mats = fresh()
+    plan = apsp.BatchPlan(mats)
+    for rep in range(2):
+        for m, W in zip(mats, Ws):
+            m.copy_(torch.from_numpy(W).to(dev))
+        plan.run()
+        torch.cuda.synchronize()
+        for m, r in zip(mats, ref):
+            assert np.array_equal(m.cpu().numpy(), r), rep
+    plan.close()
+    mats = fresh()
+    apsp.solve_batched(mats)
+    torch.cuda.synchronize()
+    for m, r in zip(mats, ref):
+        assert np.array_equal(m.cpu().numpy(), r), "one-shot"
+    mats = fresh()
+    apsp.solve_batched_noalloc(mats)
+    torch.cuda.synchronize()
+    for m, r in zip(mats, ref):
+        assert np.array_equal(m.cpu().numpy(), r), "allocation-free"
