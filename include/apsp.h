@@ -86,7 +86,13 @@ enum {
  * forms is an integer below 2^24, and the tiles are computed in fp32
  * arithmetic (exact, so the result is the same) at its higher issue rate.
  * The scan's result lives in a 256-byte device word allocated with the
- * helper streams.  From 72 rounds up (n > 9088; apsp_set_round_pair_threshold),
+ * helper streams.  From 64 rounds of 128, for calls of 16 or more rounds
+ * on 16-byte aligned rows with n a multiple of 128 (or their working copy),
+ * the call holds the int32 matrix as those fp32 values (converted in place
+ * after the scan, back at the end of the call) and runs the fp32 kernels,
+ * operands staged straight into LDS, or, when the scan rules the fp32 pipe
+ * out, the same kernels in uint32 on the untouched words.  The matrix holds
+ * int32 values again when the call's work is done.  From 72 rounds up (n > 9088; apsp_set_round_pair_threshold),
  * phase 3 runs in pairs of rounds: one pass per tile with k over both rounds' blocks, the second
  * round's update of the first round's block row and column deferred and
  * applied from a copy of its panels (the result is the same, bit for bit).

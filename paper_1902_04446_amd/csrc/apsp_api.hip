@@ -193,7 +193,12 @@ int64_t apsp_set_aligned_copy_min_n(int64_t n) {
 
 int64_t apsp_stream_state_bytes(int64_t n, int32_t dtype) {
     if (bad_dtype(dtype) || n < 0 || n >= kMaxN) return -1;
-    return apsp::stream_state_bytes(n, dtype);
+    // a full solve padded to a multiple of 128 keeps the state of the padded n
+    const int64_t b = apsp::round_width(n);
+    const int64_t q = n > 0 ? (n + b - 1) / b : 0;
+    const bool pad = n >= g_aligned_copy_min_n.load() && b == apsp::kRoundB && n % b != 0 &&
+                     q >= kPadMinMatrixRounds && q >= kPadMinRounds;
+    return apsp::stream_state_bytes(pad ? q * b : n, dtype);
 }
 
 int64_t apsp_stream_state_count(void) { return apsp::stream_state_count(); }

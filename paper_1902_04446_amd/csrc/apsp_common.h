@@ -155,7 +155,16 @@ hipError_t launch_batch_copies(const BatchCopy *copies, int32_t count, int64_t r
                                hipStream_t s);
 // Threshold of the working copies (apsp_set_aligned_copy_min_n).
 int64_t aligned_copy_min_n();
-hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s);
+// dtype of the kernels that run an int32 matrix held as the fp32 bits of
+// OpI32F (when its wmax word allows the fp32 pipe; as uint32 otherwise):
+// those kernels compute as OpF32 (or OpI32) and convert nothing.
+// launch_conv_i32 converts such a matrix in place, in (to_f32) or back.
+constexpr int kI32AsF32 = 2;
+hipError_t launch_conv_i32(uint32_t *D, int64_t n, int64_t ld, const uint32_t *wmax, bool to_f32,
+                           hipStream_t s);
+// wmax: the int32 word (dtype kI32AsF32 only)
+hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s,
+                         const uint32_t *wmax = nullptr);
 // close_next_diag (kNext only): the workgroup of diagonal block r+1 also runs
 // phase 1 of round r+1 on it before storing it.
 // wmax (int32 only): the word launch_wmax filled for this matrix; int32 tiles
@@ -228,8 +237,9 @@ hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
 // Phase 3 of rounds r and r+1 on the tiles outside blocks r .. r+1+next
 // whose block row is in [lo, hi); deferred updates as launch_pair_next.  The
 // column panels of rounds r and r+1 are in colT[first_slot] and colT[slot]
-// (read by the direct-staged fp32 kernel, which full tiles of aligned fp32
-// matrices take; the other kernels read them from the matrix).
+// (read by the direct-staged kernels, which full tiles of aligned fp32
+// matrices, and of aligned int32 matrices held as kI32AsF32, take; the other
+// kernels read them from the matrix).
 hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
                             int64_t lo, int64_t hi, int64_t prev, const PairCopies &c,
                             int prev_slot, int first_slot, int slot, hipStream_t s,
@@ -238,10 +248,12 @@ int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi);
 // Whether launch_pair_rest takes the direct-staged kernel for this matrix.
 bool pair_rest_direct(const uint32_t *D, int64_t n, int64_t ld, int dtype);
 // A single round's rest set on block rows [lo, hi) (outside block rows/columns
-// r, r+1), direct-staged: fp32, pair_rest_direct(D, ...) true, the column
-// panel of round r transposed in c.colT[col_slot] (launch_pair_panels).
-hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int64_t r, int64_t lo,
-                                   int64_t hi, const PairCopies &c, int col_slot, hipStream_t s);
+// r, r+1), direct-staged: fp32 or kI32AsF32 (wmax its word), with
+// pair_rest_direct(D, ...) true, the column panel of round r transposed in
+// c.colT[col_slot] (launch_pair_panels).
+hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                                   int64_t lo, int64_t hi, const PairCopies &c, int col_slot,
+                                   hipStream_t s, const uint32_t *wmax);
 // Round r+1's deferred phase-3 update on block row/column r: !final_: tiles
 // (x, r), (r, x) for the next blocks x; final_: every other one but the
 // blocks r+1.

@@ -149,7 +149,7 @@ __device__ __forceinline__ void pair_update(const PairArgs &a, tile::Lds &L) {
 // The rest pass of a pair with direct staging (full tiles of an aligned fp32
 // matrix): the column panels from their transposed copies, the row panels
 // from the matrix; the output tile through tile::io_direct.
-template <int MODE>
+template <class Op, int MODE>
 __device__ __forceinline__ void pair_direct_update(const PairArgs &a, tile::Lds &L) {
     const Job jb = job_of<MODE>(a);
     const int64_t i0 = (int64_t)jb.I * TB, j0 = (int64_t)jb.J * TB;
@@ -162,11 +162,11 @@ __device__ __forceinline__ void pair_direct_update(const PairArgs &a, tile::Lds 
     for (int x = jb.pending ? 0 : 1; x < 2; ++x) {
         const uint32_t *at0 = x ? a.at0 : a.pcolT, *at1 = x ? a.at1 : a.pcolT;
         const uint32_t *B = x ? a.D + (int64_t)a.r * TB * a.ld : a.prow;
-        tile::minplus_tile_direct<OpF32>(acc, at0, at1, TB, a.ldc, B, x ? a.ld : a.ldc, i0, j0,
+        tile::minplus_tile_direct<Op>(acc, at0, at1, TB, a.ldc, B, x ? a.ld : a.ldc, i0, j0,
                                          x ? jb.kblocks * TB : TB, L);
     }
     if (MODE != kRest2 && jb.close)  // phase 1 of round r+2 (kNext2) or r+1 (kNextR), fused
-        tile::close_block<OpF32>(acc, TB, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
+        tile::close_block<Op>(acc, TB, reinterpret_cast<uint32_t *>(&L.As[0][0][0]));
     uint32_t *base = a.D + i0 * a.ld + j0;
     uint32_t ld = (uint32_t)a.ld;
     asm volatile("" : "+s"(base), "+s"(ld));
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rest_direct(
     PairArgs a) {
     __shared__ tile::Lds L;
-    pair_direct_update<kRest2>(a, L);
+    pair_direct_update<OpF32, kRest2>(a, L);
 }
 
 // A single round's rest set (kRest1) in the same direct form, for matrices
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_round_rest_direct(
     PairArgs a) {
     __shared__ tile::Lds L;
-    pair_direct_update<kRest1>(a, L);
+    pair_direct_update<OpF32, kRest1>(a, L);
 }
 
 // kNext2 and kNextR (with the closure's registers: at most 152, 3 workgroups
@@ -208,27 +208,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     PairArgs a) {
     __shared__ tile::Lds L;
     tile::chain_priority();
-    pair_direct_update<MODE>(a, L);
+    pair_direct_update<OpF32, MODE>(a, L);
 }
 
-// int32 on the fp32 pipe (OpI32F, bit-identical) when *wmax allows it.
-template <int MODE>
+// The same direct-staged kernels for an int32 matrix held as kI32AsF32:
+// fp32 arithmetic on its fp32 bits when *wmax allows it (IF_EXACT, Op =
+// OpF32), uint32 arithmetic on the untouched words otherwise (Op = OpI32);
+// neither converts anything, so both stage straight into LDS.  Each pass is
+// launched as both kernels, and the one whose case does not hold returns at
+// once: one kernel holding both cases measured 123 and 155 VGPRs against the
+// 120 and 152 that keep the bands at 4 workgroups per CU and the chain's
+// workgroups able to start beside them.
+template <class Op, bool IF_EXACT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pair_rest_direct_i32(
+    PairArgs a, const uint32_t *__restrict__ wmax) {
+    if (int_exact_in_f32(a.n, *wmax) != IF_EXACT) return;
+    __shared__ tile::Lds L;
+    pair_direct_update<Op, kRest2>(a, L);
+}
+
+template <class Op, bool IF_EXACT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_round_rest_direct_i32(
+    PairArgs a, const uint32_t *__restrict__ wmax) {
+    if (int_exact_in_f32(a.n, *wmax) != IF_EXACT) return;
+    __shared__ tile::Lds L;
+    pair_direct_update<Op, kRest1>(a, L);
+}
+
+template <int MODE, class Op, bool IF_EXACT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_next_direct_i32(
+    PairArgs a, const uint32_t *__restrict__ wmax) {
+    if (int_exact_in_f32(a.n, *wmax) != IF_EXACT) return;
+    __shared__ tile::Lds L;
+    tile::chain_priority();
+    pair_direct_update<Op, MODE>(a, L);
+}
+
+// int32 on the fp32 pipe (OpI32F, bit-identical) when *wmax allows it; CONV:
+// the matrix is held as kI32AsF32, so that case computes as OpF32 with no
+// conversion.
+template <int MODE, bool CONV>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_i32(
     PairArgs a, const uint32_t *__restrict__ wmax) {
     __shared__ tile::Lds L;
     if (MODE != kRest2) tile::chain_priority();
-    if (int_exact_in_f32(a.n, *wmax))
-        pair_update<OpI32F, MODE, true>(a, L);
-    else
+    if (int_exact_in_f32(a.n, *wmax)) {
+        if (CONV)
+            pair_update<OpF32, MODE, false>(a, L);
+        else
+            pair_update<OpI32F, MODE, true>(a, L);
+    } else {
         pair_update<OpI32, MODE, false>(a, L);
+    }
 }
 
 template <int MODE>
 hipError_t launch(const PairArgs &a, int dtype, const uint32_t *wmax, unsigned grid,
                   hipStream_t s) {
     if (grid == 0) return hipSuccess;
-    if (dtype == 0 && wmax)
-        hipLaunchKernelGGL((k_pair_i32<MODE>), dim3(grid), dim3(NT), 0, s, a, wmax);
+    if (dtype == kI32AsF32)
+        hipLaunchKernelGGL((k_pair_i32<MODE, true>), dim3(grid), dim3(NT), 0, s, a, wmax);
+    else if (dtype == 0 && wmax)
+        hipLaunchKernelGGL((k_pair_i32<MODE, false>), dim3(grid), dim3(NT), 0, s, a, wmax);
     else if (dtype == 0)
         hipLaunchKernelGGL((k_pair<OpI32, MODE>), dim3(grid), dim3(NT), 0, s, a);
     else
@@ -268,7 +309,7 @@ int64_t pair_rest_count(int64_t n, int64_t r, int64_t lo, int64_t hi) {
 }
 
 bool pair_rest_direct(const uint32_t *D, int64_t n, int64_t ld, int dtype) {
-    return dtype == 1 && n % TB == 0 && (reinterpret_cast<uintptr_t>(D) & 15u) == 0 &&
+    return (dtype == 1 || dtype == kI32AsF32) && n % TB == 0 && (reinterpret_cast<uintptr_t>(D) & 15u) == 0 &&
            (ld & 3) == 0 && ld < ((int64_t)1 << 23);
 }
 
@@ -296,7 +337,13 @@ hipError_t launch_pair_next(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
     if (count > 0 && pair_rest_direct(D, n, ld, dtype)) {
         a.at0 = c.colT[first_slot];
         a.at1 = c.colT[slot];
-        hipLaunchKernelGGL(k_pair_next_direct<kNext2>, dim3(count), dim3(NT), 0, s, a);
+        if (dtype == kI32AsF32) {
+            hipLaunchKernelGGL((k_pair_next_direct_i32<kNext2, OpF32, true>), dim3(count),
+                               dim3(NT), 0, s, a, wmax);
+            hipLaunchKernelGGL((k_pair_next_direct_i32<kNext2, OpI32, false>), dim3(count),
+                               dim3(NT), 0, s, a, wmax);
+        } else
+            hipLaunchKernelGGL(k_pair_next_direct<kNext2>, dim3(count), dim3(NT), 0, s, a);
         return hipGetLastError();
     }
     return launch<kNext2>(a, dtype, wmax, count, s);
@@ -312,8 +359,14 @@ hipError_t launch_pair_round_next(uint32_t *D, int64_t n, int64_t ld, int dtype,
     a.close = 1;
     a.at0 = c.colT[first_slot];
     a.at1 = a.at0;
-    hipLaunchKernelGGL(k_pair_next_direct<kNextR>, dim3((unsigned)(2 * a.q - 3)), dim3(NT), 0, s,
-                       a);
+    if (dtype == kI32AsF32) {
+        hipLaunchKernelGGL((k_pair_next_direct_i32<kNextR, OpF32, true>),
+                           dim3((unsigned)(2 * a.q - 3)), dim3(NT), 0, s, a, wmax);
+        hipLaunchKernelGGL((k_pair_next_direct_i32<kNextR, OpI32, false>),
+                           dim3((unsigned)(2 * a.q - 3)), dim3(NT), 0, s, a, wmax);
+    } else
+        hipLaunchKernelGGL(k_pair_next_direct<kNextR>, dim3((unsigned)(2 * a.q - 3)), dim3(NT), 0,
+                           s, a);
     return hipGetLastError();
 }
 
@@ -334,14 +387,21 @@ hipError_t launch_pair_rest(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
     if (pair_rest_direct(D, n, ld, dtype)) {
         a.at0 = c.colT[first_slot];
         a.at1 = c.colT[slot];
-        hipLaunchKernelGGL(k_pair_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
+        if (dtype == kI32AsF32) {
+            hipLaunchKernelGGL((k_pair_rest_direct_i32<OpF32, true>), dim3((unsigned)count),
+                               dim3(NT), 0, s, a, wmax);
+            hipLaunchKernelGGL((k_pair_rest_direct_i32<OpI32, false>), dim3((unsigned)count),
+                               dim3(NT), 0, s, a, wmax);
+        } else
+            hipLaunchKernelGGL(k_pair_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
         return hipGetLastError();
     }
     return launch<kRest2>(a, dtype, wmax, (unsigned)count, s);
 }
 
-hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int64_t r, int64_t lo,
-                                   int64_t hi, const PairCopies &c, int col_slot, hipStream_t s) {
+hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r,
+                                   int64_t lo, int64_t hi, const PairCopies &c, int col_slot,
+                                   hipStream_t s, const uint32_t *wmax) {
     const int64_t count = tilemap::tile_count(num_rounds(n), r, kRest, lo, hi);
     if (count <= 0) return hipSuccess;
     PairArgs a = base_args(D, n, ld, (int)r, c);
@@ -349,7 +409,13 @@ hipError_t launch_round_rest_direct(uint32_t *D, int64_t n, int64_t ld, int64_t 
     a.hi = (int)hi;
     a.at0 = c.colT[col_slot];
     a.at1 = a.at0;
-    hipLaunchKernelGGL(k_round_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
+    if (dtype == kI32AsF32) {
+        hipLaunchKernelGGL((k_round_rest_direct_i32<OpF32, true>), dim3((unsigned)count), dim3(NT),
+                           0, s, a, wmax);
+        hipLaunchKernelGGL((k_round_rest_direct_i32<OpI32, false>), dim3((unsigned)count),
+                           dim3(NT), 0, s, a, wmax);
+    } else
+        hipLaunchKernelGGL(k_round_rest_direct, dim3((unsigned)count), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 

@@ -80,11 +80,10 @@ __global__ __launch_bounds__(256) void k_validate(const uint32_t *__restrict__ D
 // padded with the "no edge" value and never stored.
 // ---------------------------------------------------------------------------
 template <class Op>
-__global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64_t ld, int64_t kb,
-                                                 int kw) {
+__device__ __forceinline__ void phase1_block(uint32_t *__restrict__ D, int64_t ld, int64_t kb,
+                                             int kw) {
     __shared__ __align__(16) uint32_t rowbuf[2][TB];
     __shared__ uint32_t colbuf[2][TB];
-    tile::chain_priority();
     const int t = threadIdx.x;
     const int i = t >> 3;
     const int cg = t & 7;
@@ -128,6 +127,39 @@ __global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64
 #pragma unroll
         for (int u = 0; u < 16; ++u)
             if (c0 + u < kw) rowp[c0 + u] = v[u];
+    }
+}
+
+template <class Op>
+__global__ __launch_bounds__(1024) void k_phase1(uint32_t *__restrict__ D, int64_t ld, int64_t kb,
+                                                 int kw) {
+    tile::chain_priority();
+    phase1_block<Op>(D, ld, kb, kw);
+}
+
+// int32 matrix held as fp32 bits (OpI32F's form) when *wmax allows it, as
+// uint32 otherwise (converted by launch_conv_i32 before the first round).
+__global__ __launch_bounds__(1024) void k_phase1_conv(uint32_t *__restrict__ D, int64_t ld,
+                                                      int64_t n, int64_t kb, int kw,
+                                                      const uint32_t *__restrict__ wmax) {
+    tile::chain_priority();
+    if (int_exact_in_f32(n, *wmax))
+        phase1_block<OpF32>(D, ld, kb, kw);
+    else
+        phase1_block<OpI32>(D, ld, kb, kw);
+}
+
+// int32 <-> the fp32 bits OpI32F computes on, in place, when *wmax allows
+// the fp32 pipe (else nothing): to_f32 v -> (float)min(v, 2^30), back
+// f -> min((uint32)f, 2^30).  Thread = column, rows strided by the grid's y.
+__global__ __launch_bounds__(256) void k_conv_i32(uint32_t *__restrict__ D, int64_t n, int64_t ld,
+                                                  const uint32_t *__restrict__ wmax, int to_f32) {
+    if (!int_exact_in_f32(n, *wmax)) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        uint32_t *p = D + i * ld + j;
+        *p = to_f32 ? OpI32F::norm(*p) : OpI32F::out(*p);
     }
 }
 
@@ -175,7 +207,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 // int32: on the fp32 pipe (OpI32F, bit-identical) when the matrix's largest
 // finite entry *wmax allows it, else in uint32.
-template <int MODE>
+// CONV: the matrix is held as fp32 bits when *wmax allows the fp32 pipe
+// (launch_conv_i32), so those tiles compute as OpF32 with no conversion.
+template <int MODE, bool CONV>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_tiles_i32(
     uint32_t *__restrict__ D, int64_t ld, int64_t n, int r, int q, int vec, int close_diag,
     int row_lo, int row_hi, const uint32_t *__restrict__ wmax) {
@@ -183,10 +217,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     if (MODE == kPanels || MODE == kNext) tile::chain_priority();
     int I, J;
     tile_of<MODE>(r, q, row_lo, row_hi, I, J);
-    if (int_exact_in_f32(n, *wmax))
-        tile_update<OpI32F, MODE, true>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
-    else
+    if (int_exact_in_f32(n, *wmax)) {
+        if (CONV)
+            tile_update<OpF32, MODE, false>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+        else
+            tile_update<OpI32F, MODE, true>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+    } else {
         tile_update<OpI32, MODE, false>(D, ld, n, r, I, J, vec != 0, close_diag != 0, L);
+    }
 }
 
 __global__ void k_zero_word(uint32_t *w) { *w = 0u; }
@@ -222,23 +260,33 @@ inline bool aligned16(const void *p, int64_t ld) {
 
 inline unsigned grid_rows(int64_t n) { return (unsigned)(n < 8192 ? n : 8192); }
 
-void launch_tiles_i32(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec,
-                      int close, int lo, int hi, const uint32_t *wmax, hipStream_t s,
-                      unsigned grid) {
+template <bool CONV>
+void launch_tiles_i32_as(int set, uint32_t *D, int64_t n, int64_t ld, int r, int q, int vec,
+                         int close, int lo, int hi, const uint32_t *wmax, hipStream_t s,
+                         unsigned grid) {
     switch (set) {
     case kPanels:
-        hipLaunchKernelGGL((k_tiles_i32<kPanels>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        hipLaunchKernelGGL((k_tiles_i32<kPanels, CONV>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
         break;
     case kAll:
-        hipLaunchKernelGGL((k_tiles_i32<kAll>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        hipLaunchKernelGGL((k_tiles_i32<kAll, CONV>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
         break;
     case kNext:
-        hipLaunchKernelGGL((k_tiles_i32<kNext>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        hipLaunchKernelGGL((k_tiles_i32<kNext, CONV>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
         break;
     default:
-        hipLaunchKernelGGL((k_tiles_i32<kRest>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
+        hipLaunchKernelGGL((k_tiles_i32<kRest, CONV>), dim3(grid), dim3(NT), 0, s, D, ld, n, r, q, vec, close, lo, hi, wmax);
         break;
     }
+}
+
+void launch_tiles_i32(bool conv, int set, uint32_t *D, int64_t n, int64_t ld, int r, int q,
+                      int vec, int close, int lo, int hi, const uint32_t *wmax, hipStream_t s,
+                      unsigned grid) {
+    if (conv)
+        launch_tiles_i32_as<true>(set, D, n, ld, r, q, vec, close, lo, hi, wmax, s, grid);
+    else
+        launch_tiles_i32_as<false>(set, D, n, ld, r, q, vec, close, lo, hi, wmax, s, grid);
 }
 
 template <class Op>
@@ -289,11 +337,22 @@ int64_t tile_count(int64_t n, int64_t r, int set) {
     return tilemap::tile_count(q, r, set, 0, q);
 }
 
-hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s) {
+hipError_t launch_conv_i32(uint32_t *D, int64_t n, int64_t ld, const uint32_t *wmax, bool to_f32,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256), grid_rows(n));
+    hipLaunchKernelGGL(k_conv_i32, grid, dim3(256), 0, s, D, n, ld, wmax, to_f32 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase1(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r, hipStream_t s,
+                         const uint32_t *wmax) {
     const int64_t kb = r * TB;
     if (kb >= n) return hipSuccess;
     const int kw = (int)((n - kb) < TB ? (n - kb) : TB);
-    if (dtype == 0)
+    if (dtype == kI32AsF32)
+        hipLaunchKernelGGL(k_phase1_conv, dim3(1), dim3(1024), 0, s, D, ld, n, kb, kw, wmax);
+    else if (dtype == 0)
         hipLaunchKernelGGL(k_phase1<OpI32>, dim3(1), dim3(1024), 0, s, D, ld, kb, kw);
     else
         hipLaunchKernelGGL(k_phase1<OpF32>, dim3(1), dim3(1024), 0, s, D, ld, kb, kw);
@@ -307,8 +366,9 @@ hipError_t launch_tile_set(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_
     const int q = (int)num_rounds(n);
     const int vec = aligned16(D, ld) ? 1 : 0;
     const int close = ((set == kNext || set == kAll) && close_next_diag) ? 1 : 0;
-    if (dtype == 0 && wmax)
-        launch_tiles_i32(set, D, n, ld, (int)r, q, vec, close, 0, q, wmax, s, (unsigned)count);
+    if ((dtype == 0 || dtype == kI32AsF32) && wmax)
+        launch_tiles_i32(dtype == kI32AsF32, set, D, n, ld, (int)r, q, vec, close, 0, q, wmax, s,
+                         (unsigned)count);
     else if (dtype == 0)
         launch_tiles<OpI32>(set, D, n, ld, (int)r, q, vec, close, 0, q, s, (unsigned)count);
     else
@@ -337,9 +397,9 @@ hipError_t launch_rest_rows(uint32_t *D, int64_t n, int64_t ld, int dtype, int64
     if (count <= 0) return hipSuccess;
     const int q = (int)num_rounds(n);
     const int vec = aligned16(D, ld) ? 1 : 0;
-    if (dtype == 0 && wmax)
-        launch_tiles_i32(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, wmax, s,
-                         (unsigned)count);
+    if ((dtype == 0 || dtype == kI32AsF32) && wmax)
+        launch_tiles_i32(dtype == kI32AsF32, kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi,
+                         wmax, s, (unsigned)count);
     else if (dtype == 0)
         launch_tiles<OpI32>(kRest, D, n, ld, (int)r, q, vec, 0, (int)lo, (int)hi, s, (unsigned)count);
     else

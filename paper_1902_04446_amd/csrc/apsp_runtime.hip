@@ -82,6 +82,11 @@ constexpr int64_t kW64LookaheadRounds = APSP_W64_LOOKAHEAD_ROUNDS;
 // rounds and win 2% at 72, 7% at 128.  Settable per process
 // (apsp_set_round_pair_threshold).
 constexpr int64_t kDefaultPairRounds = 72;
+// int32 solves held as fp32 bits (kI32AsF32): from this many rounds of the
+// matrix and of the call (the two conversion passes then cost well under
+// what the direct-staged fp32 kernels gain).
+constexpr int64_t kConvMinRounds = 64;
+constexpr int64_t kConvMinCallRounds = 16;
 std::atomic<int64_t> g_pair_rounds{kDefaultPairRounds};
 // Matrices of at most this many vertices run rounds of width 64
 // (apsp_small.hip): below it a solve is bound by the chain of dependent
@@ -226,11 +231,13 @@ bool uses_pairs(int64_t n) {
     return b == kRoundB && uses_lookahead(n) && q >= g_pair_rounds.load() && q >= 2;
 }
 
-// Whether a full solve of an fp32 matrix of n vertices runs single rounds of
-// 128 with the direct-staged rest set (which needs the transposed column
-// copies), given 16-byte aligned rows.
+// Whether a full solve of an fp32 matrix of n vertices (or an int32 one held
+// as fp32 bits, from kConvMinRounds rounds) runs single rounds of 128 with
+// the direct-staged rest set (which needs the transposed column copies),
+// given 16-byte aligned rows.
 bool uses_direct_single(int64_t n, int dtype) {
-    return dtype == 1 && n % kRoundB == 0 && round_width(n) == kRoundB && uses_lookahead(n) &&
+    return (dtype == 1 || (dtype == 0 && (n + kRoundB - 1) / kRoundB >= kConvMinRounds)) &&
+           n % kRoundB == 0 && round_width(n) == kRoundB && uses_lookahead(n) &&
            !uses_pairs(n);
 }
 
@@ -351,6 +358,14 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     if ((lookahead || dtype == 0) && !h) return herr;
     // int32: the tiles take the fp32 pipe when this matrix allows it exactly
     const uint32_t *wmax = dtype == 0 ? h->word : nullptr;
+    // int32 with rounds of 128 on aligned full tiles, from 64 rounds and for
+    // a call of 16 or more: the matrix is held as the fp32 bits OpI32F
+    // computes on for the call (converted in after the weight scan when that
+    // scan allows the fp32 pipe, back at the end), so the fp32 kernels, with
+    // their direct staging, run it (kI32AsF32).
+    const bool conv = dtype == 0 && !w64 && lookahead && q >= kConvMinRounds &&
+                      r1 - r0 >= kConvMinCallRounds && pair_rest_direct(D, n, ld, kI32AsF32);
+    const int dt = conv ? kI32AsF32 : dtype;  // the dtype the round kernels take
     std::unique_lock<std::mutex> lock;
     if (h) lock = std::unique_lock<std::mutex>(h->mu);
     // Pairs run on the helper streams, which exist from 3 rounds on (below
@@ -362,7 +377,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     // phase 3 reads it with both operands staged straight into LDS.  The next
     // writer of a slot is phase 2 of round r+2, which follows the wait for
     // round r's rest set on S.
-    const bool direct1 = !w64 && lookahead && !pairs && pair_rest_direct(D, n, ld, dtype) &&
+    const bool direct1 = !w64 && lookahead && !pairs && pair_rest_direct(D, n, ld, dt) &&
                          ensure_copies(h, n, s);
     if (lookahead) {
         // S = the chain stream, after the caller's earlier work
@@ -376,15 +391,16 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     }
     // the phase launches at this width
     auto phase1 = [&](int64_t r) {
-        return w64 ? launch_phase1_64(D, n, ld, dtype, r, s) : launch_phase1(D, n, ld, dtype, r, s);
+        return w64 ? launch_phase1_64(D, n, ld, dtype, r, s)
+                   : launch_phase1(D, n, ld, dt, r, s, wmax);
     };
     auto tile_set = [&](int64_t r, int set, bool close_next) {
         return w64 ? launch_tile_set64(D, n, ld, dtype, r, set, s, close_next, wmax, 0, q)
-                   : launch_tile_set(D, n, ld, dtype, r, set, s, close_next, wmax);
+                   : launch_tile_set(D, n, ld, dt, r, set, s, close_next, wmax);
     };
     auto rest_rows = [&](int64_t r, int64_t lo, int64_t hi, hipStream_t st) {
         return w64 ? launch_tile_set64(D, n, ld, dtype, r, kRest, st, false, wmax, lo, hi)
-                   : launch_rest_rows(D, n, ld, dtype, r, lo, hi, st, wmax);
+                   : launch_rest_rows(D, n, ld, dt, r, lo, hi, st, wmax);
     };
 
     // Timing: spans of enqueued work on a stream, by category (the PhaseTimes
@@ -432,6 +448,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
     };
     if (prologue) chk(launch_prologue(D, n, ld, dtype, s));
     if (wmax) chk(launch_wmax(D, n, ld, h->word, s));
+    if (conv) chk(launch_conv_i32(D, n, ld, h->word, true, s));
     if (times) rec(t_pro, s);
 
     bool rest_pending = false;
@@ -453,7 +470,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         diag_closed = false;
         sp = open(2, s);
         if (direct1)
-            chk(launch_pair_panels(D, n, ld, dtype, r, h->copies, -1, (int)(r & 1), s, wmax));
+            chk(launch_pair_panels(D, n, ld, dt, r, h->copies, -1, (int)(r & 1), s, wmax));
         else
             chk(tile_set(r, kPanels, false));
         close(sp, s);
@@ -484,7 +501,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 rest_pending = false;
                 if (prev >= 0) {
                     const size_t sp = open(7, s);
-                    chk(launch_pair_fix(D, n, ld, dtype, prev, true, s, wmax));
+                    chk(launch_pair_fix(D, n, ld, dt, prev, true, s, wmax));
                     close(sp, s);
                     prev = -1;
                 }
@@ -498,27 +515,27 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
             const int nx = pair_next_blocks(n, r);
             {  // phases 1-2 of round r, its block column copied transposed
                 size_t sp1 = open(1, s);
-                if (!diag_closed) chk(launch_phase1(D, n, ld, dtype, r, s));
+                if (!diag_closed) chk(launch_phase1(D, n, ld, dt, r, s, wmax));
                 close(sp1, s);
                 diag_closed = false;
                 sp1 = open(2, s);
-                chk(launch_pair_panels(D, n, ld, dtype, r, h->copies, -1, first, s, wmax));
+                chk(launch_pair_panels(D, n, ld, dt, r, h->copies, -1, first, s, wmax));
                 close(sp1, s);
             }
             size_t sp = open(7, s);
-            chk(launch_pair_round_next(D, n, ld, dtype, r, h->copies, first, s, wmax));
+            chk(launch_pair_round_next(D, n, ld, dt, r, h->copies, first, s, wmax));
             close(sp, s);
             sp = open(2, s);
-            chk(launch_pair_panels(D, n, ld, dtype, r + 1, h->copies, slot, slot, s, wmax));
+            chk(launch_pair_panels(D, n, ld, dt, r + 1, h->copies, slot, slot, s, wmax));
             close(sp, s);
             chk(hipEventRecord(h->p2_done, s));
             wait_rest(s);
             const bool close_next = nx > 0 && r + 2 < r1;
             sp = open(7, s);
             if (nx > 0) {
-                chk(launch_pair_next(D, n, ld, dtype, r, close_next, prev, h->copies, prev_slot,
+                chk(launch_pair_next(D, n, ld, dt, r, close_next, prev, h->copies, prev_slot,
                                      first, slot, s, wmax));
-                chk(launch_pair_fix(D, n, ld, dtype, r, false, s, wmax));
+                chk(launch_pair_fix(D, n, ld, dt, r, false, s, wmax));
             }
             close(sp, s);
             diag_closed = close_next;
@@ -535,7 +552,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 band_range(g, lo, hi);
                 chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                 const size_t b = open(5, h->side[g]);
-                chk(launch_pair_rest(D, n, ld, dtype, r, lo, hi, prev, h->copies, prev_slot,
+                chk(launch_pair_rest(D, n, ld, dt, r, lo, hi, prev, h->copies, prev_slot,
                                      first, slot, h->side[g], wmax));
                 close(b, h->side[g]);
                 chk(hipEventRecord(h->rest_done[g], h->side[g]));
@@ -551,7 +568,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         wait_rest(s);
         if (prev >= 0 && err == hipSuccess) {
             const size_t sp = open(7, s);
-            chk(launch_pair_fix(D, n, ld, dtype, prev, true, s, wmax));
+            chk(launch_pair_fix(D, n, ld, dt, prev, true, s, wmax));
             close(sp, s);
         }
     } else {
@@ -566,7 +583,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                 wait_rest(s);
                 size_t sp = open(7, s);
                 if (direct1 && fuse)  // (the direct form always closes block r+1)
-                    chk(launch_pair_round_next(D, n, ld, dtype, r, h->copies, (int)(r & 1), s,
+                    chk(launch_pair_round_next(D, n, ld, dt, r, h->copies, (int)(r & 1), s,
                                                wmax));
                 else
                     chk(tile_set(r, kNext, fuse));
@@ -589,8 +606,8 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
                     chk(hipStreamWaitEvent(h->side[g], h->p2_done, 0));
                     const size_t b = open(5, h->side[g]);
                     if (direct1)
-                        chk(launch_round_rest_direct(D, n, ld, r, lo, hi, h->copies, (int)(r & 1),
-                                                     h->side[g]));
+                        chk(launch_round_rest_direct(D, n, ld, dt, r, lo, hi, h->copies,
+                                                     (int)(r & 1), h->side[g], wmax));
                     else
                         chk(rest_rows(r, lo, hi, h->side[g]));
                     close(b, h->side[g]);
@@ -612,6 +629,7 @@ hipError_t run_rounds(uint32_t *D, int64_t n, int64_t ld, int dtype, int64_t r0,
         }
         wait_rest(s);
     }
+    if (conv && err == hipSuccess) chk(launch_conv_i32(D, n, ld, h->word, false, s));
     if (s != caller) {  // the caller's stream waits for S (which waited for every band)
         chk(hipEventRecord(h->leave, s));
         chk(hipStreamWaitEvent(caller, h->leave, 0));

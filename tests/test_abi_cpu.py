@@ -226,9 +226,10 @@ def test_stream_state_bytes(lib):
     """No HIP call: the per-stream state a full solve creates.  fp32 solves
     below the lookahead (16 rounds of 64) keep none; int32 solves keep the
     256-byte scan word; from 72 rounds of 128 the pair copies, 8 x 128 x 128q
-    words, come on top, and so do they for fp32 single rounds of 128 with
+    words, come on top, and so do they for single rounds of 128 with
     n % 128 == 0 (the direct-staged rest set reads their transposed column
-    slots)."""
+    slots) in fp32, and in int32 from 64 rounds (held as fp32 bits); from 64
+    rounds a ragged n is solved padded to a multiple of 128."""
     f32, i32 = 1, 0
     assert lib.apsp_stream_state_bytes(0, f32) == 0
     assert lib.apsp_stream_state_bytes(1000, f32) == 0
@@ -236,16 +237,26 @@ def test_stream_state_bytes(lib):
     # 64 rounds of 128, single rounds with the direct-staged rest set: the
     # transposed column copies come with the state (fp32, n % 128 == 0)
     assert lib.apsp_stream_state_bytes(8192, f32) == 256 + 8 * 128 * 8192 * 4
-    assert lib.apsp_stream_state_bytes(8100, f32) == 256       # ragged: register-staged
-    assert lib.apsp_stream_state_bytes(8192, i32) == 256       # int32: register-staged
+    # 64 rounds with n % 128 != 0: solved padded to 8192, the copies of 8192
+    assert lib.apsp_stream_state_bytes(8100, f32) == 256 + 8 * 128 * 8192 * 4
+    assert lib.apsp_stream_state_bytes(8000, f32) == 256       # 63 rounds: register-staged
+    # int32 from 64 rounds is held as fp32 bits and runs the direct-staged kernels
+    assert lib.apsp_stream_state_bytes(8192, i32) == 256 + 8 * 128 * 8192 * 4
+    assert lib.apsp_stream_state_bytes(8064, i32) == 256       # 63 rounds: int32 kernels
     assert lib.apsp_stream_state_bytes(16384, f32) == 256 + 8 * 128 * 16384 * 4
     assert lib.apsp_stream_state_bytes(16385, i32) == 256 + 8 * 128 * 16512 * 4
     assert lib.apsp_stream_state_bytes(100, 7) == -1
     assert lib.apsp_stream_state_bytes(-1, f32) == -1
     prev = lib.apsp_set_round_pair_threshold(1 << 20)  # no pairs at any size
     try:
-        assert lib.apsp_stream_state_bytes(16385, i32) == 256
+        assert lib.apsp_stream_state_bytes(16385, i32) == 256 + 8 * 128 * 16512 * 4
         assert lib.apsp_stream_state_bytes(16384, f32) == 256 + 8 * 128 * 16384 * 4
+        prev_copy = lib.apsp_set_aligned_copy_min_n(1 << 40)  # no working copies
+        try:
+            assert lib.apsp_stream_state_bytes(16385, i32) == 256   # ragged: int32 kernels
+            assert lib.apsp_stream_state_bytes(8100, f32) == 256
+        finally:
+            lib.apsp_set_aligned_copy_min_n(prev_copy)
     finally:
         lib.apsp_set_round_pair_threshold(prev)
     assert lib.apsp_stream_state_count() >= 0

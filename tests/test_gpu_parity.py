@@ -1299,3 +1299,32 @@ def test_batched_working_copies(aligned_copy_threshold, dev, dtype):
     torch.cuda.synchronize()
     for m, r in zip(mats, ref):
         assert np.array_equal(m.cpu().numpy(), r), "allocation-free"
+
+
+@pytest.mark.parametrize("n,whi", [(8192, 100), (8192, 1 << 20), (9216, 100), (9216, 1 << 20)])
+def test_int32_held_as_fp32(apsp, dev, n, whi):
+    """int32 calls of 16 or more rounds on matrices of 64 or more rounds of
+    128 hold the matrix as OpI32F's fp32 bits (when the weight scan allows
+    the fp32 pipe) and run the direct-staged kernels; calls of fewer rounds
+    run the int32 kernels on the integers.  A whole solve (one call) equals
+    the same solve in slices of 8 rounds bit for bit, and sampled rows and
+    columns equal integer Dijkstra.  8192 runs single rounds of 128, 9216
+    round pairs; U{1..100} takes the fp32 pipe, U{1..2^20} uint32."""
+    import torch
+
+    rng = gg.rng_for(gg.CFG_TEST, 1700 + whi + n)
+    u, v, w = gg.er_edges(n, 6.0 / n, 1, whi, rng)
+    full = gg.device_dense_from_edges(n, u, v, w, np.int32, dev)
+    sliced = full.clone()
+    apsp.solve(full)
+    q = apsp.num_rounds(n)
+    for r0 in range(0, q, 8):
+        apsp.solve_rounds(sliced, r0, r0 + 8)
+    torch.cuda.synchronize()
+    assert torch.equal(full, sliced)
+    csr = gg.csr_from_edges(n, u, v, w)
+    src = np.unique(np.concatenate([rng.choice(n, size=12, replace=False), [n - 1]]))
+    ref = oracle.dijkstra(csr, n, src, threads=16, integer=True)
+    tsrc = torch.as_tensor(src, device=dev)
+    assert np.array_equal(full[tsrc].cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(full[:, tsrc].cpu().numpy().T.astype(np.int64), ref)
