@@ -113,7 +113,7 @@ enum {
  * padded to 4 elements and, for a matrix of 64 or more rounds of 128
  * (n > 8064) and a call of 16 or more rounds, n padded to a multiple of 128
  * with vertices that have no edges (which changes no operation on the real
- * entries).  The copy (at most n' x n' words, n' the
+ * entries) when that adds at most 1 % to n.  The copy (at most n' x n' words, n' the
  * padded n) comes from hipMallocAsync on `stream`, is filled, solved and
  * copied back in stream order, and is freed with hipFreeAsync behind that
  * work; when it cannot be allocated the call runs in place.  The result is

@@ -52,7 +52,8 @@ int32_t check_matrix(const void *dist, int64_t n, int64_t ld, int32_t dtype) {
 //    17.0 ms; n = 16461: 124.4 against 115.8 ms).  Below 64 rounds the
 //    padding and the copies cost what the staging gains (n = 5200: 6.11
 //    against 6.09 ms; n = 6000: 7.80 against 7.77 ms), so only matrices of 64
-//    or more rounds are padded.
+//    or more rounds are padded, and only by at most 1 % more vertices
+//    (pads_to_128).
 // From g_aligned_copy_min_n vertices such a call runs on a working copy: rows
 // padded to 4 elements, and, for the second case, n padded to a multiple of
 // 128 with vertices that have no edges (+inf, or 2^30, off the diagonal; 0 on
@@ -73,15 +74,25 @@ constexpr int64_t kPadMinRounds = 16;     // rounds in the call
 constexpr int64_t kPadMinMatrixRounds = 64;  // rounds of the whole matrix
 std::atomic<int64_t> g_aligned_copy_min_n{kDefaultAlignedCopyMinN};
 
+// Whether a matrix of n vertices is worth padding to a multiple of 128: rounds
+// of 128, 64 or more of them, and at most 1 % more vertices (up to about 3 %
+// more work against the 6-7 % the staging gains: n = 8193, padded to 8320,
+// measured 17.74 against 17.65 ms in place).
+bool pads_to_128(int64_t n) {
+    const int64_t b = apsp::round_width(n);
+    if (b != apsp::kRoundB || n % b == 0 || (n + b - 1) / b < kPadMinMatrixRounds) return false;
+    const int64_t extra = b - n % b;
+    return 100 * extra <= n;
+}
+
 // The vertex count of the working copy of a call of `rounds` rounds on this
 // matrix, or 0 when the call runs in place.
 int64_t working_n(const void *dist, int64_t n, int64_t ld, int64_t rounds) {
     if (n <= 0 || n < g_aligned_copy_min_n.load()) return 0;
     const bool aligned = (reinterpret_cast<uintptr_t>(dist) & 15u) == 0 && (ld & 3) == 0;
-    const int64_t b = apsp::round_width(n);
-    const bool pad = b == apsp::kRoundB && n % b != 0 && rounds >= kPadMinRounds &&
-                     (n + b - 1) / b >= kPadMinMatrixRounds;
+    const bool pad = rounds >= kPadMinRounds && pads_to_128(n);
     if (aligned && !pad) return 0;
+    const int64_t b = apsp::kRoundB;
     return pad ? (n + b - 1) / b * b : n;
 }
 
@@ -194,11 +205,9 @@ int64_t apsp_set_aligned_copy_min_n(int64_t n) {
 int64_t apsp_stream_state_bytes(int64_t n, int32_t dtype) {
     if (bad_dtype(dtype) || n < 0 || n >= kMaxN) return -1;
     // a full solve padded to a multiple of 128 keeps the state of the padded n
-    const int64_t b = apsp::round_width(n);
-    const int64_t q = n > 0 ? (n + b - 1) / b : 0;
-    const bool pad = n >= g_aligned_copy_min_n.load() && b == apsp::kRoundB && n % b != 0 &&
-                     q >= kPadMinMatrixRounds && q >= kPadMinRounds;
-    return apsp::stream_state_bytes(pad ? q * b : n, dtype);
+    const bool pad = n >= g_aligned_copy_min_n.load() && pads_to_128(n);
+    const int64_t b = apsp::kRoundB;
+    return apsp::stream_state_bytes(pad ? (n + b - 1) / b * b : n, dtype);
 }
 
 int64_t apsp_stream_state_count(void) { return apsp::stream_state_count(); }

@@ -237,8 +237,10 @@ def test_stream_state_bytes(lib):
     # 64 rounds of 128, single rounds with the direct-staged rest set: the
     # transposed column copies come with the state (fp32, n % 128 == 0)
     assert lib.apsp_stream_state_bytes(8192, f32) == 256 + 8 * 128 * 8192 * 4
-    # 64 rounds with n % 128 != 0: solved padded to 8192, the copies of 8192
-    assert lib.apsp_stream_state_bytes(8100, f32) == 256 + 8 * 128 * 8192 * 4
+    # 64 rounds with n % 128 != 0: solved padded to a multiple of 128 when that
+    # adds at most 1 % to n (8150 -> 8192), in place otherwise (8100)
+    assert lib.apsp_stream_state_bytes(8150, f32) == 256 + 8 * 128 * 8192 * 4
+    assert lib.apsp_stream_state_bytes(8100, f32) == 256
     assert lib.apsp_stream_state_bytes(8000, f32) == 256       # 63 rounds: register-staged
     # int32 from 64 rounds is held as fp32 bits and runs the direct-staged kernels
     assert lib.apsp_stream_state_bytes(8192, i32) == 256 + 8 * 128 * 8192 * 4
@@ -254,7 +256,7 @@ def test_stream_state_bytes(lib):
         prev_copy = lib.apsp_set_aligned_copy_min_n(1 << 40)  # no working copies
         try:
             assert lib.apsp_stream_state_bytes(16385, i32) == 256   # ragged: int32 kernels
-            assert lib.apsp_stream_state_bytes(8100, f32) == 256
+            assert lib.apsp_stream_state_bytes(8150, f32) == 256
         finally:
             lib.apsp_set_aligned_copy_min_n(prev_copy)
     finally:
