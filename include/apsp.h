@@ -202,7 +202,9 @@ int32_t apsp_solve_rounds(void *dist, int64_t n, int64_t ld, int32_t dtype, int6
  *   [7] the other phase-3 launches on `stream` (block rows/columns r+1 ..
  *       r+3 and the deferred updates), summed
  * Phase-3 launches overlap phases 1 and 2 of the next round (one-round
- * lookahead), so [1] + [2] + [3] can exceed [4].  The result in `dist` is
+ * lookahead), so [1] + [2] + [3] can exceed [4].  When the call runs on a
+ * working copy (see apsp_solve) the phases time the solve on the copy, and
+ * the copies in and back are outside them.  The result in `dist` is
  * identical to apsp_solve's.  phase_ms must have room for 8 values.
  * Synchronous.  Returns as apsp_solve.
  */
